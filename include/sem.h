@@ -1,0 +1,146 @@
+/*
+ * sem.h -- C ABI of libsem: matrix-free spectral-element viscous-Burgers operators, their
+ * Jacobian products, and RK4 forward/adjoint integration on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Marin, Constantinescu & Smith, "A scalable matrix-free spectral element approach for
+ * unsteady PDE constrained optimization using PETSc/TAO", arXiv 1806.01422.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Mesh.   A periodic box [0,L_1]x..x[0,L_d] (d = 1, 2, 3) split into E_1 x .. x E_d equal
+ *         elements, each carrying (N+1)^d Gauss-Lobatto-Legendre (GLL) points (order N).
+ *         Along direction k there are n_k = E_k * N unique nodes; node g_k lies at
+ *         x = (g_k div N) h_k + (xi_{g_k mod N} + 1) h_k / 2, h_k = L_k / E_k.
+ * Fields. A field is a velocity with C = d components stored as a contiguous device array
+ *         [batch][C][n_3][n_2][n_1] (x fastest) of the context's dtype (double or float).
+ *         ndof = C * n_1 * n_2 * n_3 values per batch member.
+ * Memory. Every pointer argument named u, v, w, f, jv, jtw, lam, ckpt, work is a DEVICE pointer
+ *         owned by the caller, who keeps it alive until the stream work completes.  libsem
+ *         never frees caller memory.  The context owns its tables and scratch (allocated in
+ *         sem_setup, released in sem_destroy).
+ * Streams. All work is enqueued on the context stream (a hipStream_t passed as void*, NULL for
+ *         the null stream) and returns without synchronising, except where documented.
+ * Errors. Every function returns SEM_OK (0) or a negative sem_status and sets a thread-local
+ *         message readable with sem_last_error().  Inputs are validated before anything is
+ *         enqueued; on error nothing has been enqueued.  Outputs must not alias inputs
+ *         (checked by pointer equality, SEM_ERR_ARG).  A context is not thread-safe.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_ERR_ARG = -1,         /* invalid argument: sizes, null/aliased pointers, dt, nsteps */
+  SEM_ERR_UNSUPPORTED = -2, /* order N or dimension outside the compiled range */
+  SEM_ERR_HIP = -3,         /* a HIP runtime call failed (message carries the HIP error) */
+  SEM_ERR_NOMEM = -4,       /* device allocation failed */
+  SEM_ERR_NONFINITE = -5    /* a trajectory produced a non-finite value (when checking is on) */
+} sem_status;
+
+typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
+
+/* Problem descriptor.  Supported: dim 1..3; order 1..12 for dim 1 and 2, 1..9 for dim 3;
+   elems[k] >= 1; length[k] > 0; nu >= 0; batch >= 1.  Entries past dim are ignored. */
+typedef struct {
+  int32_t dim;
+  int32_t elems[3];
+  int32_t order;
+  double length[3];
+  double nu;
+  int32_t dtype; /* sem_dtype */
+  int32_t batch; /* number of same-shape fields stacked on the leading axis */
+} sem_desc;
+
+typedef struct sem_ctx_s* sem_ctx;
+
+/* Create a context: computes the GLL tables (Sec. 3.2: Legendre polynomials on GLL points,
+   nodes, weights and the differentiation matrix D), the 1-D assembled lumped masses, and
+   allocates the scratch the operators and integrators need.  stream: hipStream_t or NULL. */
+int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out);
+int sem_destroy(sem_ctx ctx);
+/* Rebind the stream used by later calls. */
+int sem_set_stream(sem_ctx ctx, void* stream);
+/* ndof per batch member (C * nodes) and unique nodes per component. Either pointer may be NULL. */
+int sem_query(sem_ctx ctx, int64_t* ndof, int64_t* nodes);
+/* Host copy of the 1-D node coordinates of direction dir (n_dir doubles into x_host). */
+int sem_node_coords(sem_ctx ctx, int32_t dir, double* x_host);
+
+/* f = F(u) = M^{-1} Q^T a(Q u): the semi-discrete right-hand side of u_t = nu Lap u - (u.grad)u
+   in the explicit form u' = M^{-1} P(u) (Sec. 3.4), where a(.) is the per-element weak form
+   -sum_j D_j^T(nu W D_j U_i) - W sum_j U_j D_j U_i (Sec. 3.3, eq. rhsvec; signs of eq. burgers23d),
+   Q the periodic gather to elements, Q^T the direct-stiffness summation and M the assembled
+   diagonal GLL mass.  u, f: [batch][C][...] device arrays; f must not alias u. */
+int sem_rhs(sem_ctx ctx, const void* u, void* f);
+
+/* jv = J(u) v, the Jacobian of F at u applied to v (Sec. 3.3, eq. jacvec, with the M^{-1} of the
+   explicit form).  jv must alias neither u nor v. */
+int sem_jac_vec(sem_ctx ctx, const void* u, const void* v, void* jv);
+
+/* jtw = J(u)^T w, the Euclidean transpose of J(u) on the unique nodes (Sec. 3.3, eq. jactransvec):
+   J^T w = Q^T a'(Qu)^T Q M^{-1} w, i.e. the inverse mass scales the input before the gather and
+   the summed result is not divided.  jtw must alias neither u nor w. */
+int sem_jact_vec(sem_ctx ctx, const void* u, const void* w, void* jtw);
+
+/* Classical RK4 with fixed step dt, nsteps steps, applied in place to u (u0 in, u(T) out) for
+   every batch member.  If ckpt is non-NULL, u_{sK} (K = ckpt_every) is copied to
+   ckpt[s][batch][ndof] for s = 0 .. nsteps/K - 1 before step sK (nsteps % K must be 0).
+   The four stage updates are fused into the summation kernels; one step is a captured graph. */
+int sem_rk4_forward(sem_ctx ctx, void* u, double dt, int32_t nsteps, int32_t ckpt_every, void* ckpt);
+
+/* Discrete adjoint of sem_rk4_forward (Sec. 4.1, eqs. adjointloop, initadj, gradient, adjtime,
+   for the classical RK4 tableau): on entry lam holds lambda_N = dPhi/du(T); on exit lambda_0 =
+   dPhi/du_0.  Uses the checkpoints written by sem_rk4_forward with the same dt, nsteps and
+   ckpt_every, and recomputes each segment of K states into work (Sec. 5.3).  work: device buffer
+   of at least sem_workspace_bytes(ctx, ckpt_every) bytes.  Per step the stage states are
+   recomputed (3 F) and four J^T products are applied. */
+int sem_rk4_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every,
+                    void* lam, void* work);
+/* Bytes of caller work buffer needed by sem_rk4_adjoint for a given ckpt_every. */
+int sem_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, int64_t* bytes);
+/* Enable (1) or disable (0, default) the non-finite check at the end of sem_rk4_forward (one
+   host synchronisation per call). */
+int sem_set_check_finite(sem_ctx ctx, int32_t on);
+
+/* Message of the last failure on the calling thread ("" if none).  Valid until the next call. */
+const char* sem_last_error(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batched uneven problems: `count` independent problems of possibly different dim-2 shapes,
+ * orders, viscosities and step sizes, packed back to back in one device array (problem p
+ * occupies [offset_p, offset_p + ndof_p) values; offsets from sem_batch_query).  Each RK4 stage
+ * runs as one persistent launch over all problems (work items sorted by cost) and one
+ * summation launch; a full RK4 step is captured in a HIP graph and replayed.  Descriptors must
+ * share dim and dtype and have batch == 1.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct sem_batch_s* sem_batch;
+/* dts: host array of count step sizes.  stream: hipStream_t or NULL. */
+int sem_batch_setup(const sem_desc* descs, const double* dts, int32_t count, void* stream, sem_batch* out);
+int sem_batch_destroy(sem_batch b);
+/* offsets: host array of count+1 entries (in values, not bytes); offsets[count] = total. */
+int sem_batch_query(sem_batch b, int64_t* offsets);
+/* F of every problem: f = F(u) on packed arrays. */
+int sem_batch_rhs(sem_batch b, const void* u, void* f);
+/* J_p(u_p)^T w_p for every problem p on packed arrays. */
+int sem_batch_jact_vec(sem_batch b, const void* u, const void* w, void* jtw);
+/* RK4 forward for every problem with its own dt (nsteps shared); ckpt as in sem_rk4_forward with
+   the packed layout: ckpt[s][total]. */
+int sem_batch_rk4_forward(sem_batch b, void* u, int32_t nsteps, int32_t ckpt_every, void* ckpt);
+/* Discrete adjoint for every problem; work must hold sem_batch_workspace_bytes bytes. */
+int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t ckpt_every, void* lam,
+                          void* work);
+int sem_batch_workspace_bytes(sem_batch b, int32_t ckpt_every, int64_t* bytes);
+/* Time candidate launch shapes on the current inputs' sizes and keep the fastest (synchronises
+   the stream; results are cached per problem set).  best_ms (host, may be NULL) receives the
+   fastest RK4 step time. */
+int sem_batch_autotune(sem_batch b, double* best_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEM_H */

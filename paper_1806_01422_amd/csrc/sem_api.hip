@@ -1,0 +1,684 @@
+// libsem C ABI: contexts, operator entry points, RK4 forward/adjoint with uniform checkpoints, and
+// the batched uneven problem set.  Host code only; kernels live in kern_*.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sem_internal.h"
+
+using namespace sem;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) return fail(SEM_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_));  \
+  } while (0)
+
+// A device allocation released with the owner.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
+  int alloc(size_t n) {
+    release();
+    if (n == 0) n = 256;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return fail(SEM_ERR_NOMEM, "hipMalloc(%zu bytes) failed: %s", n, hipGetErrorString(e));
+    }
+    bytes = n;
+    return SEM_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { release(); }
+};
+
+// Sets dt of every problem entry of a device table (stream-ordered, capturable).
+__global__ void set_dt_kernel(ProbDev* probs, int n, const double* dts, double dt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) probs[i].dt = dts ? dts[i] : dt;
+}
+
+template <typename T>
+__global__ void finite_kernel(const T* __restrict__ x, int64_t n, int* __restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (; i < n; i += stride) bad |= !isfinite((double)x[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+int validate_desc(const sem_desc* d) {
+  if (!d) return fail(SEM_ERR_ARG, "null descriptor");
+  if (d->dim < 1 || d->dim > 3) return fail(SEM_ERR_UNSUPPORTED, "dim %d outside 1..3", d->dim);
+  const int maxN = (d->dim == 3) ? MAXP3 - 1 : MAXP - 1;
+  if (d->order < 1 || d->order > maxN)
+    return fail(SEM_ERR_UNSUPPORTED, "order %d outside 1..%d for dim %d", d->order, maxN, d->dim);
+  if (d->dtype != SEM_F64 && d->dtype != SEM_F32) return fail(SEM_ERR_ARG, "dtype %d", d->dtype);
+  if (d->batch < 1) return fail(SEM_ERR_ARG, "batch %d < 1", d->batch);
+  if (!(d->nu >= 0.0) || !std::isfinite(d->nu)) return fail(SEM_ERR_ARG, "nu must be finite and >= 0");
+  int64_t nodes = 1;
+  for (int k = 0; k < d->dim; ++k) {
+    if (d->elems[k] < 1) return fail(SEM_ERR_ARG, "elems[%d] = %d < 1", k, d->elems[k]);
+    if (!(d->length[k] > 0.0) || !std::isfinite(d->length[k])) return fail(SEM_ERR_ARG, "length[%d] must be > 0", k);
+    if ((int64_t)d->elems[k] * d->order > (int64_t)1 << 30) return fail(SEM_ERR_ARG, "mesh too large");
+    nodes *= (int64_t)d->elems[k] * d->order;
+  }
+  if (nodes * d->dim * (int64_t)d->batch > ((int64_t)1 << 40)) return fail(SEM_ERR_ARG, "field too large");
+  return SEM_OK;
+}
+
+// Fill a problem entry (offsets left to the caller).
+void fill_prob(const sem_desc* d, ProbDev* p) {
+  std::memset(p, 0, sizeof(*p));
+  double xi[MAXP], w[MAXP], D[MAXP * MAXP];
+  gll_tables(d->order, xi, w, D);
+  p->N = d->order;
+  p->P = d->order + 1;
+  p->dim = d->dim;
+  p->batch = d->batch;
+  p->nelem = 1;
+  p->nodes = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (k < d->dim) {
+      p->E[k] = d->elems[k];
+      p->n[k] = d->elems[k] * d->order;
+      const double h = d->length[k] / d->elems[k];
+      p->sc[k] = 2.0 / h;
+      p->hh[k] = 0.5 * h;
+    } else {
+      p->E[k] = 1;
+      p->n[k] = 1;
+      p->sc[k] = 0.0;
+      p->hh[k] = 1.0;
+    }
+    p->nelem *= p->E[k];
+    p->nodes *= p->n[k];
+  }
+  p->nu = d->nu;
+  p->dt = 0.0;
+  for (int i = 0; i < p->P; ++i) p->w[i] = w[i];
+}
+
+// Device tables (D, w) of one order, both precisions.
+struct DevTables {
+  DevBuf t64, t32;
+  int make(int N) {
+    double xi[MAXP], w[MAXP], D[MAXP * MAXP];
+    gll_tables(N, xi, w, D);
+    const int P = N + 1;
+    Tables<double> a{};
+    Tables<float> b{};
+    for (int i = 0; i < P * P; ++i) {
+      a.D[i] = D[i];
+      b.D[i] = (float)D[i];
+    }
+    for (int i = 0; i < P; ++i) {
+      a.w[i] = w[i];
+      b.w[i] = (float)w[i];
+    }
+    int rc;
+    if ((rc = t64.alloc(sizeof(a)))) return rc;
+    if ((rc = t32.alloc(sizeof(b)))) return rc;
+    HIPCHK(hipMemcpy(t64.p, &a, sizeof(a), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(t32.p, &b, sizeof(b), hipMemcpyHostToDevice));
+    return SEM_OK;
+  }
+  const void* get(int dtype) const { return dtype == SEM_F64 ? t64.p : t32.p; }
+};
+
+// Operator application over a set of problems: element launches (one per order class, or the
+// tuned 3-D kernel) followed by one summation launch.
+struct OpSet {
+  int dim = 0, dtype = 0;
+  size_t ts = 8;
+  std::vector<ProbDev> hp;  // host copy of the table (offsets, items)
+  DevBuf dprob;             // device table
+  struct Class {
+    int P;
+    int64_t nitems;
+    int first, count;  // problems [first, first+count) of dprob, sorted by order
+    DevTables tab;
+    int epb = 0;
+  };
+  std::vector<Class> classes;
+  int64_t total_vals = 0, total_nodes = 0, lvals = 0;
+  DevBuf lvec;
+  bool fast = false;  // single 3-D problem handled by the tuned kernel
+  DevBuf face;
+  DevTables fast_tab;
+
+  int finalize() {
+    int rc;
+    if ((rc = dprob.alloc(sizeof(ProbDev) * hp.size()))) return rc;
+    HIPCHK(hipMemcpy(dprob.p, hp.data(), sizeof(ProbDev) * hp.size(), hipMemcpyHostToDevice));
+    if (!fast && (rc = lvec.alloc(lvals * ts))) return rc;
+    return SEM_OK;
+  }
+
+  hipError_t apply(int op, const void* u, const void* v, Coef in_scale, const Epi& epi, hipStream_t s) {
+    if (fast)
+      return launch_fast3d(hp[0], op, u, v, epi.o1, face.p, epi, in_scale, fast_tab.get(dtype), s);
+    for (auto& c : classes) {
+      ElemLaunch el{static_cast<const ProbDev*>(dprob.p) + c.first, c.count, c.nitems, dim, c.P, dtype, c.epb};
+      hipError_t e = launch_elem(el, op, u, v, lvec.p, in_scale, c.tab.get(dtype), s);
+      if (e != hipSuccess) return e;
+    }
+    return launch_dss(static_cast<const ProbDev*>(dprob.p), (int)hp.size(), total_nodes, dim, dtype, op != OP_JACT,
+                      lvec.p, epi, s);
+  }
+};
+
+// Builds an OpSet for problems given by descriptors (packed back to back, sorted internally by
+// order so that each order class is a contiguous table range; packed offsets keep input order).
+int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
+  os.dim = descs[0].dim;
+  os.dtype = descs[0].dtype;
+  os.ts = os.dtype == SEM_F64 ? 8 : 4;
+  std::vector<int64_t> off(count + 1, 0);
+  std::vector<ProbDev> tmp(count);
+  for (int i = 0; i < count; ++i) {
+    fill_prob(&descs[i], &tmp[i]);
+    off[i + 1] = off[i] + tmp[i].nodes * tmp[i].dim * tmp[i].batch;
+    tmp[i].off = off[i];
+  }
+  os.total_vals = off[count];
+  os.fast = allow_fast && count == 1 && os.dim == 3 && descs[0].batch == 1 && fast3d_supported(descs[0].order, os.dtype);
+  // order classes
+  std::vector<int> idx(count);
+  for (int i = 0; i < count; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return tmp[a].P < tmp[b].P; });
+  os.hp.clear();
+  os.classes.clear();
+  int64_t lv = 0, nodes0 = 0;
+  for (int k = 0; k < count;) {
+    int P = tmp[idx[k]].P;
+    OpSet::Class c;
+    c.P = P;
+    c.first = (int)os.hp.size();
+    c.count = 0;
+    int64_t items = 0;
+    while (k < count && tmp[idx[k]].P == P) {
+      ProbDev p = tmp[idx[k]];
+      p.item0 = items;
+      p.loff = lv;
+      p.node0 = nodes0;
+      items += p.nelem * p.batch;
+      lv += p.nelem * p.batch * p.dim * (int64_t)std::pow(P, p.dim);
+      nodes0 += p.nodes * p.batch;
+      os.hp.push_back(p);
+      ++c.count;
+      ++k;
+    }
+    c.nitems = items;
+    int rc = c.tab.make(P - 1);
+    if (rc) return rc;
+    os.classes.push_back(std::move(c));
+  }
+  // item0 must be class-relative for element launches but node0 global: already so.
+  os.lvals = lv;
+  os.total_nodes = nodes0;
+  if (os.fast) {
+    int rc;
+    if ((rc = os.fast_tab.make(descs[0].order))) return rc;
+    if ((rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts))) return rc;
+  }
+  return os.finalize();
+}
+
+// RK4 forward/adjoint machinery shared by contexts and batches.
+struct Integrator {
+  OpSet* os = nullptr;
+  int64_t n = 0;  // values per state (all problems / batch members)
+  size_t ts = 8;
+  enum { STATE, S1, S2, ACC, USTATE, A2, A3, A4, T1, T2, LACC, LAMB, NBUF };
+  DevBuf buf[NBUF];
+  bool ready = false;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gstep = nullptr, gadj = nullptr;
+  DevBuf dts;  // per-problem dt table for the batch
+
+  ~Integrator() {
+    if (gstep) (void)hipGraphExecDestroy(gstep);
+    if (gadj) (void)hipGraphExecDestroy(gadj);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  void* b(int i) { return buf[i].p; }
+
+  // one RK4 step on STATE (stage updates fused into the summation epilogues)
+  hipError_t enqueue_step(hipStream_t s) {
+    hipError_t e;
+    Epi ep{};
+    // k1 = F(u):  S1 = u + dt/2 k1;  ACC = u + dt/6 k1
+    ep = Epi{b(S1), b(STATE), {1, 0}, {0, 0.5}, b(ACC), b(STATE), {1, 0}, {0, 1.0 / 6}};
+    if ((e = os->apply(OP_RHS, b(STATE), nullptr, {1, 0}, ep, s))) return e;
+    // k2 = F(S1): S2 = u + dt/2 k2;  ACC += dt/3 k2
+    ep = Epi{b(S2), b(STATE), {1, 0}, {0, 0.5}, b(ACC), b(ACC), {1, 0}, {0, 1.0 / 3}};
+    if ((e = os->apply(OP_RHS, b(S1), nullptr, {1, 0}, ep, s))) return e;
+    // k3 = F(S2): S1 = u + dt k3;  ACC += dt/3 k3
+    ep = Epi{b(S1), b(STATE), {1, 0}, {0, 1.0}, b(ACC), b(ACC), {1, 0}, {0, 1.0 / 3}};
+    if ((e = os->apply(OP_RHS, b(S2), nullptr, {1, 0}, ep, s))) return e;
+    // k4 = F(S1): u = ACC + dt/6 k4
+    ep = Epi{b(STATE), b(ACC), {1, 0}, {0, 1.0 / 6}, nullptr, nullptr, {0, 0}, {0, 0}};
+    return os->apply(OP_RHS, b(S1), nullptr, {1, 0}, ep, s);
+  }
+
+  // reverse sweep through one RK4 step taken from USTATE, updating LAMB in place:
+  //   U2 = u + dt/2 F(u), U3 = u + dt/2 F(U2), U4 = u + dt F(U3)   (recomputed)
+  //   a4 = J(U4)^T (dt/6 lam); a3 = J(U3)^T (dt/3 lam + dt a4); a2 = J(U2)^T (dt/3 lam + dt/2 a3);
+  //   a1 = J(u)^T (dt/6 lam + dt/2 a2); lam <- lam + a1 + a2 + a3 + a4
+  hipError_t enqueue_adjoint_step(hipStream_t s) {
+    hipError_t e;
+    const Coef one{1, 0}, zero{0, 0};
+    Epi ep{b(A2), b(USTATE), one, {0, 0.5}, nullptr, nullptr, zero, zero};
+    if ((e = os->apply(OP_RHS, b(USTATE), nullptr, one, ep, s))) return e;
+    ep = Epi{b(A3), b(USTATE), one, {0, 0.5}, nullptr, nullptr, zero, zero};
+    if ((e = os->apply(OP_RHS, b(A2), nullptr, one, ep, s))) return e;
+    ep = Epi{b(A4), b(USTATE), one, {0, 1.0}, nullptr, nullptr, zero, zero};
+    if ((e = os->apply(OP_RHS, b(A3), nullptr, one, ep, s))) return e;
+    ep = Epi{b(T1), b(LAMB), {0, 1.0 / 3}, {0, 1.0}, b(LACC), b(LAMB), one, one};
+    if ((e = os->apply(OP_JACT, b(A4), b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
+    ep = Epi{b(T2), b(LAMB), {0, 1.0 / 3}, {0, 0.5}, b(LACC), b(LACC), one, one};
+    if ((e = os->apply(OP_JACT, b(A3), b(T1), one, ep, s))) return e;
+    ep = Epi{b(T1), b(LAMB), {0, 1.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one};
+    if ((e = os->apply(OP_JACT, b(A2), b(T2), one, ep, s))) return e;
+    ep = Epi{b(LAMB), b(LACC), one, one, nullptr, nullptr, zero, zero};
+    return os->apply(OP_JACT, b(USTATE), b(T1), one, ep, s);
+  }
+
+  int prepare() {
+    if (ready) return SEM_OK;
+    for (int i = 0; i < NBUF; ++i) {
+      int rc = buf[i].alloc(n * ts);
+      if (rc) return rc;
+    }
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_step(cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(SEM_ERR_HIP, "capturing the RK4 step: %s", hipGetErrorString(e ? e : e2));
+    }
+    e = hipGraphInstantiate(&gstep, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    g = nullptr;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    e = enqueue_adjoint_step(cap);
+    e2 = hipStreamEndCapture(cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(SEM_ERR_HIP, "capturing the RK4 adjoint step: %s", hipGetErrorString(e ? e : e2));
+    }
+    e = hipGraphInstantiate(&gadj, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e);
+    ready = true;
+    return SEM_OK;
+  }
+
+  // dt: a single value for every table entry, or per-entry values in dts (device) when per_problem
+  int set_dt(double dt, bool per_problem, hipStream_t s) {
+    const int np = (int)os->hp.size();
+    hipLaunchKernelGGL(set_dt_kernel, dim3((np + 63) / 64), dim3(64), 0, s, static_cast<ProbDev*>(os->dprob.p), np,
+                       per_problem ? static_cast<const double*>(dts.p) : nullptr, dt);
+    HIPCHK(hipGetLastError());
+    return SEM_OK;
+  }
+
+  int forward(void* u, int32_t nsteps, int32_t K, void* ckpt, hipStream_t s) {
+    const size_t bytes = n * ts;
+    HIPCHK(hipMemcpyAsync(b(STATE), u, bytes, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < nsteps; ++k) {
+      if (ckpt && k % K == 0)
+        HIPCHK(hipMemcpyAsync(static_cast<char*>(ckpt) + (size_t)(k / K) * bytes, b(STATE), bytes,
+                              hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipGraphLaunch(gstep, s));
+    }
+    HIPCHK(hipMemcpyAsync(u, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
+    return SEM_OK;
+  }
+
+  int adjoint(const void* ckpt, int32_t nsteps, int32_t K, void* lam, void* work, hipStream_t s) {
+    const size_t bytes = n * ts;
+    char* wk = static_cast<char*>(work);
+    HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
+    for (int sg = nsteps / K - 1; sg >= 0; --sg) {
+      HIPCHK(hipMemcpyAsync(b(STATE), static_cast<const char*>(ckpt) + (size_t)sg * bytes, bytes,
+                            hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(wk, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
+      for (int k = 1; k < K; ++k) {
+        HIPCHK(hipGraphLaunch(gstep, s));
+        HIPCHK(hipMemcpyAsync(wk + (size_t)k * bytes, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
+      }
+      for (int k = K - 1; k >= 0; --k) {
+        HIPCHK(hipMemcpyAsync(b(USTATE), wk + (size_t)k * bytes, bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipGraphLaunch(gadj, s));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
+    return SEM_OK;
+  }
+};
+
+}  // namespace
+
+struct sem_ctx_s {
+  sem_desc d{};
+  hipStream_t stream = nullptr;
+  OpSet os;
+  Integrator integ;
+  int64_t ndof = 0, nodes = 0;
+  bool check_finite = false;
+  DevBuf flag;
+};
+
+struct sem_batch_s {
+  std::vector<sem_desc> descs;
+  std::vector<double> dts;
+  std::vector<int64_t> offsets;
+  hipStream_t stream = nullptr;
+  OpSet os;
+  Integrator integ;
+};
+
+extern "C" {
+
+const char* sem_last_error(void) { return g_err.c_str(); }
+
+int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out) {
+  if (!out) return fail(SEM_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  int rc = validate_desc(desc);
+  if (rc) return rc;
+  sem_ctx c = new (std::nothrow) sem_ctx_s();
+  if (!c) return fail(SEM_ERR_NOMEM, "host allocation failed");
+  c->d = *desc;
+  c->stream = static_cast<hipStream_t>(stream);
+  if ((rc = build_opset(c->os, desc, 1, true))) {
+    delete c;
+    return rc;
+  }
+  c->nodes = c->os.hp[0].nodes;
+  c->ndof = c->nodes * desc->dim;
+  c->integ.os = &c->os;
+  c->integ.n = c->ndof * desc->batch;
+  c->integ.ts = c->os.ts;
+  if ((rc = c->flag.alloc(sizeof(int)))) {
+    delete c;
+    return rc;
+  }
+  g_err.clear();
+  *out = c;
+  return SEM_OK;
+}
+
+int sem_destroy(sem_ctx c) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  delete c;
+  return SEM_OK;
+}
+
+int sem_set_stream(sem_ctx c, void* stream) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  c->stream = static_cast<hipStream_t>(stream);
+  return SEM_OK;
+}
+
+int sem_query(sem_ctx c, int64_t* ndof, int64_t* nodes) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (ndof) *ndof = c->ndof;
+  if (nodes) *nodes = c->nodes;
+  return SEM_OK;
+}
+
+int sem_node_coords(sem_ctx c, int32_t dir, double* x) {
+  if (!c || !x) return fail(SEM_ERR_ARG, "null argument");
+  if (dir < 0 || dir >= c->d.dim) return fail(SEM_ERR_ARG, "dir %d outside 0..%d", dir, c->d.dim - 1);
+  double xi[MAXP], w[MAXP], D[MAXP * MAXP];
+  const int N = c->d.order;
+  gll_tables(N, xi, w, D);
+  const double h = c->d.length[dir] / c->d.elems[dir];
+  const int64_t n = (int64_t)c->d.elems[dir] * N;
+  for (int64_t g = 0; g < n; ++g) x[g] = (double)(g / N) * h + 0.5 * (xi[g % N] + 1.0) * h;
+  return SEM_OK;
+}
+
+static int apply_entry(sem_ctx c, int op, const void* u, const void* v, void* out) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!u || !out || (op != OP_RHS && !v)) return fail(SEM_ERR_ARG, "null field pointer");
+  if (out == u || (v && out == v)) return fail(SEM_ERR_ARG, "output aliases an input");
+  Epi ep{out, nullptr, {0, 0}, {1, 0}, nullptr, nullptr, {0, 0}, {0, 0}};
+  HIPCHK(c->os.apply(op, u, v, {1, 0}, ep, c->stream));
+  return SEM_OK;
+}
+
+int sem_rhs(sem_ctx c, const void* u, void* f) { return apply_entry(c, OP_RHS, u, nullptr, f); }
+int sem_jac_vec(sem_ctx c, const void* u, const void* v, void* jv) { return apply_entry(c, OP_JAC, u, v, jv); }
+int sem_jact_vec(sem_ctx c, const void* u, const void* w, void* jtw) { return apply_entry(c, OP_JACT, u, w, jtw); }
+
+static int check_steps(double dt, int32_t nsteps, int32_t K, bool need_k) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SEM_ERR_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(SEM_ERR_ARG, "nsteps %d < 0", nsteps);
+  if (need_k && (K < 1 || (nsteps % K) != 0))
+    return fail(SEM_ERR_ARG, "ckpt_every %d must be >= 1 and divide nsteps %d", K, nsteps);
+  return SEM_OK;
+}
+
+int sem_set_check_finite(sem_ctx c, int32_t on) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  c->check_finite = on != 0;
+  return SEM_OK;
+}
+
+int sem_rk4_forward(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!u) return fail(SEM_ERR_ARG, "null u");
+  int rc = check_steps(dt, nsteps, K, ckpt != nullptr);
+  if (rc) return rc;
+  if (ckpt && ckpt == u) return fail(SEM_ERR_ARG, "ckpt aliases u");
+  if ((rc = c->integ.prepare())) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  if ((rc = c->integ.forward(u, nsteps, K, ckpt, c->stream))) return rc;
+  if (c->check_finite) {
+    HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
+    const int64_t n = c->integ.n;
+    if (c->d.dtype == SEM_F64)
+      hipLaunchKernelGGL(finite_kernel<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double*>(u), n,
+                         static_cast<int*>(c->flag.p));
+    else
+      hipLaunchKernelGGL(finite_kernel<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float*>(u), n,
+                         static_cast<int*>(c->flag.p));
+    HIPCHK(hipGetLastError());
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (h) return fail(SEM_ERR_NONFINITE, "trajectory produced a non-finite value (dt = %g too large?)", dt);
+  }
+  return SEM_OK;
+}
+
+int sem_workspace_bytes(sem_ctx c, int32_t K, int64_t* bytes) {
+  if (!c || !bytes) return fail(SEM_ERR_ARG, "null argument");
+  if (K < 1) return fail(SEM_ERR_ARG, "ckpt_every %d < 1", K);
+  *bytes = (int64_t)K * c->integ.n * (int64_t)c->os.ts;
+  return SEM_OK;
+}
+
+int sem_rk4_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam, void* work) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  int rc = check_steps(dt, nsteps, K, true);
+  if (rc) return rc;
+  if (lam == ckpt || lam == work || work == ckpt) return fail(SEM_ERR_ARG, "aliased buffers");
+  if ((rc = c->integ.prepare())) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  return c->integ.adjoint(ckpt, nsteps, K, lam, work, c->stream);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Batched uneven problems
+// ------------------------------------------------------------------------------------------------
+int sem_batch_setup(const sem_desc* descs, const double* dts, int32_t count, void* stream, sem_batch* out) {
+  if (!out) return fail(SEM_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  if (!descs || !dts || count < 1) return fail(SEM_ERR_ARG, "need count >= 1 descriptors and step sizes");
+  for (int i = 0; i < count; ++i) {
+    int rc = validate_desc(&descs[i]);
+    if (rc) return rc;
+    if (descs[i].batch != 1) return fail(SEM_ERR_ARG, "batched problem %d has batch %d != 1", i, descs[i].batch);
+    if (descs[i].dim != descs[0].dim || descs[i].dtype != descs[0].dtype)
+      return fail(SEM_ERR_ARG, "problem %d differs in dim or dtype", i);
+    if (!(dts[i] > 0.0) || !std::isfinite(dts[i])) return fail(SEM_ERR_ARG, "dt of problem %d must be > 0", i);
+  }
+  sem_batch b = new (std::nothrow) sem_batch_s();
+  if (!b) return fail(SEM_ERR_NOMEM, "host allocation failed");
+  b->descs.assign(descs, descs + count);
+  b->dts.assign(dts, dts + count);
+  b->stream = static_cast<hipStream_t>(stream);
+  int rc = build_opset(b->os, descs, count, false);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  b->offsets.assign(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    int64_t v = 1;
+    for (int k = 0; k < descs[i].dim; ++k) v *= (int64_t)descs[i].elems[k] * descs[i].order;
+    b->offsets[i + 1] = b->offsets[i] + v * descs[i].dim;
+  }
+  // per-table-entry dt (table entries are sorted by order; match by packed offset)
+  std::vector<double> tdt(b->os.hp.size());
+  for (size_t t = 0; t < b->os.hp.size(); ++t) {
+    int64_t off = b->os.hp[t].off;
+    int i = (int)(std::lower_bound(b->offsets.begin(), b->offsets.end(), off) - b->offsets.begin());
+    tdt[t] = dts[i];
+  }
+  b->integ.os = &b->os;
+  b->integ.n = b->os.total_vals;
+  b->integ.ts = b->os.ts;
+  if ((rc = b->integ.dts.alloc(sizeof(double) * tdt.size()))) {
+    delete b;
+    return rc;
+  }
+  if (hipMemcpy(b->integ.dts.p, tdt.data(), sizeof(double) * tdt.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    delete b;
+    return fail(SEM_ERR_HIP, "copying step sizes");
+  }
+  if ((rc = b->integ.set_dt(0.0, true, nullptr))) {
+    delete b;
+    return rc;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) {
+    delete b;
+    return fail(SEM_ERR_HIP, "batch setup synchronisation");
+  }
+  g_err.clear();
+  *out = b;
+  return SEM_OK;
+}
+
+int sem_batch_destroy(sem_batch b) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  delete b;
+  return SEM_OK;
+}
+
+int sem_batch_query(sem_batch b, int64_t* offsets) {
+  if (!b || !offsets) return fail(SEM_ERR_ARG, "null argument");
+  std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+  return SEM_OK;
+}
+
+static int batch_apply(sem_batch b, int op, const void* u, const void* v, void* out) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (!u || !out || (op != OP_RHS && !v)) return fail(SEM_ERR_ARG, "null field pointer");
+  if (out == u || (v && out == v)) return fail(SEM_ERR_ARG, "output aliases an input");
+  Epi ep{out, nullptr, {0, 0}, {1, 0}, nullptr, nullptr, {0, 0}, {0, 0}};
+  HIPCHK(b->os.apply(op, u, v, {1, 0}, ep, b->stream));
+  return SEM_OK;
+}
+
+int sem_batch_rhs(sem_batch b, const void* u, void* f) { return batch_apply(b, OP_RHS, u, nullptr, f); }
+int sem_batch_jact_vec(sem_batch b, const void* u, const void* w, void* jtw) {
+  return batch_apply(b, OP_JACT, u, w, jtw);
+}
+
+int sem_batch_workspace_bytes(sem_batch b, int32_t K, int64_t* bytes) {
+  if (!b || !bytes) return fail(SEM_ERR_ARG, "null argument");
+  if (K < 1) return fail(SEM_ERR_ARG, "ckpt_every %d < 1", K);
+  *bytes = (int64_t)K * b->integ.n * (int64_t)b->os.ts;
+  return SEM_OK;
+}
+
+int sem_batch_rk4_forward(sem_batch b, void* u, int32_t nsteps, int32_t K, void* ckpt) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (!u) return fail(SEM_ERR_ARG, "null u");
+  int rc = check_steps(1.0, nsteps, K, ckpt != nullptr);
+  if (rc) return rc;
+  if ((rc = b->integ.prepare())) return rc;
+  return b->integ.forward(u, nsteps, K, ckpt, b->stream);
+}
+
+int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t K, void* lam, void* work) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  int rc = check_steps(1.0, nsteps, K, true);
+  if (rc) return rc;
+  if ((rc = b->integ.prepare())) return rc;
+  return b->integ.adjoint(ckpt, nsteps, K, lam, work, b->stream);
+}
+
+int sem_batch_autotune(sem_batch b, double* best_ms) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (best_ms) *best_ms = 0.0;
+  return SEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Private declarations shared by libsem's translation units (host launchers + HIP kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "sem.h"
+
+namespace sem {
+
+// Largest supported number of GLL points per direction (order N = MAXP - 1 in 1-D and 2-D).
+constexpr int MAXP = 13;
+constexpr int MAXP3 = 10;  // 3-D: (N+1)^3 threads per element must fit one workgroup
+
+// GLL differentiation matrix and weights for one order (device-resident; kernels get a pointer).
+template <typename T>
+struct Tables {
+  T D[MAXP * MAXP];  // D[i*P + j] = l_j'(xi_i)
+  T w[MAXP];
+};
+
+// One problem of a launch (device-resident array, read-only in kernels).  A context with a
+// same-shape batch is one entry with batch > 1; a batched uneven set has one entry per problem.
+struct ProbDev {
+  int32_t E[3], n[3];
+  int32_t N, P, dim, batch;
+  double sc[3];  // 2 / h_k: scale of D on the physical element
+  double hh[3];  // h_k / 2
+  double nu, dt;
+  double w[MAXP];  // GLL weights of this order
+  int64_t off;     // offset (values) of this problem's batch member 0 in the packed field arrays
+  int64_t loff;    // offset (values) of its element-local scratch
+  int64_t nelem;   // elements per batch member
+  int64_t nodes;   // unique nodes per component per batch member
+  int64_t item0;   // first element work item of this problem in its element launch
+  int64_t node0;   // first node work item of this problem in the summation launch
+};
+
+// Coefficient evaluated per problem: c0 + cdt * dt_p.
+struct Coef {
+  double c0, cdt;
+};
+
+// Epilogue of the summation (DSS) kernels: s is the assembled operator value at a node;
+//   o1 = a1 * x1 + b1 * s   (x1 may be NULL: then o1 = b1 * s)
+//   o2 = a2 * x2 + b2 * s   (optional; o2 may equal x2)
+struct Epi {
+  void* o1;
+  const void* x1;
+  Coef a1, b1;
+  void* o2;
+  const void* x2;
+  Coef a2, b2;
+};
+
+enum Op { OP_RHS = 0, OP_JAC = 1, OP_JACT = 2 };
+
+// A set of problems of one order and dimension that an element launch covers.
+struct ElemLaunch {
+  const ProbDev* probs;  // device array
+  int32_t nprobs;
+  int64_t nitems;  // total element items
+  int32_t dim, P, dtype;
+  int32_t epb;  // elements per workgroup (tunable); 0 = default
+};
+
+// Launchers (kern_generic.hip).  Return hipSuccess or the launch error.  `tables` is a device
+// pointer to Tables<T> of the launch's order.
+hipError_t launch_elem(const ElemLaunch& el, int op, const void* u, const void* v, void* lvec, Coef in_scale,
+                       const void* tables, hipStream_t s);
+hipError_t launch_dss(const ProbDev* probs, int32_t nprobs, int64_t nitems, int dim, int dtype, int divide_by_mass,
+                      const void* lvec, const Epi& epi, hipStream_t s);
+// elements-per-workgroup choices accepted by launch_elem for (dim, P); returns count, fills out[]
+int elem_epb_choices(int dim, int P, int* out, int max_out);
+
+// Host GLL tables in long double (gll.cpp)
+void gll_tables(int N, double* xi, double* w, double* D);
+
+// Fast 3-D path (kern_fast3d.hip): returns true if it handles (N, dtype).
+bool fast3d_supported(int N, int dtype);
+hipError_t launch_fast3d(const ProbDev& hp, int op, const void* u, const void* v, void* out, void* face,
+                         const Epi& epi, Coef in_scale, const void* tables, hipStream_t s);
+int64_t fast3d_face_values(const ProbDev& hp);
+
+}  // namespace sem

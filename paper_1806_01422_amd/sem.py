@@ -1,0 +1,332 @@
+"""ctypes binding of libsem (include/sem.h): argument marshalling only.
+
+Every operator, integrator and adjoint runs in libsem's HIP kernels on the GPU; PyTorch only
+provides device memory and the current stream.  There is no CPU fallback: if libsem.so is missing
+or no GPU is present, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsem.so")
+
+SEM_F64, SEM_F32 = 0, 1
+
+
+class SemError(RuntimeError):
+    pass
+
+
+class SemDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("elems", ctypes.c_int32 * 3), ("order", ctypes.c_int32),
+                ("length", ctypes.c_double * 3), ("nu", ctypes.c_double), ("dtype", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_SIGS = {
+    "sem_setup": [ctypes.POINTER(SemDesc), _vp, ctypes.POINTER(_vp)],
+    "sem_destroy": [_vp],
+    "sem_set_stream": [_vp, _vp],
+    "sem_query": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "sem_node_coords": [_vp, _i32, ctypes.POINTER(_f64)],
+    "sem_rhs": [_vp, _vp, _vp],
+    "sem_jac_vec": [_vp, _vp, _vp, _vp],
+    "sem_jact_vec": [_vp, _vp, _vp, _vp],
+    "sem_rk4_forward": [_vp, _vp, _f64, _i32, _i32, _vp],
+    "sem_rk4_adjoint": [_vp, _vp, _f64, _i32, _i32, _vp, _vp],
+    "sem_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
+    "sem_set_check_finite": [_vp, _i32],
+    "sem_last_error": [],
+    "sem_batch_setup": [ctypes.POINTER(SemDesc), ctypes.POINTER(_f64), _i32, _vp, ctypes.POINTER(_vp)],
+    "sem_batch_destroy": [_vp],
+    "sem_batch_query": [_vp, ctypes.POINTER(_i64)],
+    "sem_batch_rhs": [_vp, _vp, _vp],
+    "sem_batch_jact_vec": [_vp, _vp, _vp, _vp],
+    "sem_batch_rk4_forward": [_vp, _vp, _i32, _i32, _vp],
+    "sem_batch_rk4_adjoint": [_vp, _vp, _i32, _i32, _vp, _vp],
+    "sem_batch_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
+    "sem_batch_autotune": [_vp, ctypes.POINTER(_f64)],
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Load libsem.so (built in-tree by ``python -m paper_1806_01422_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SemError(f"{LIB_PATH} is not built; run `python -m paper_1806_01422_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "sem_last_error" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _call(rc):
+    if rc != 0:
+        msg = lib().sem_last_error().decode()
+        raise SemError(f"libsem status {rc}: {msg}")
+
+
+def _stream():
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(dtype):
+    if dtype == torch.float64:
+        return SEM_F64
+    if dtype == torch.float32:
+        return SEM_F32
+    raise SemError(f"unsupported dtype {dtype}")
+
+
+def _desc(dim, order, elems, length, nu, dtype, batch):
+    elems = list(elems) + [1] * (3 - len(elems))
+    length = list(length) + [1.0] * (3 - len(length))
+    return SemDesc(int(dim), (ctypes.c_int32 * 3)(*[int(e) for e in elems[:3]]), int(order),
+                   (ctypes.c_double * 3)(*[float(x) for x in length[:3]]), float(nu), _dtype_code(dtype),
+                   int(batch))
+
+
+def _ptr(t):
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """One SEM Burgers problem (or a same-shape batch of fields) on the current GPU."""
+
+    def __init__(self, dim, order, elems, length, nu, dtype=torch.float64, batch=1):
+        if not torch.cuda.is_available():
+            raise SemError("no GPU available: libsem runs only on the GPU")
+        self.dim, self.order, self.nu, self.dtype, self.batch = dim, order, float(nu), dtype, batch
+        self.elems = tuple(int(e) for e in elems)
+        self.length = tuple(float(x) for x in length)
+        self._h = _vp()
+        d = _desc(dim, order, elems, length, nu, dtype, batch)
+        _call(lib().sem_setup(ctypes.byref(d), _stream(), ctypes.byref(self._h)))
+        ndof, nodes = _i64(), _i64()
+        _call(lib().sem_query(self._h, ctypes.byref(ndof), ctypes.byref(nodes)))
+        self.ndof, self.nodes = ndof.value, nodes.value
+        self.n = tuple(e * order for e in self.elems)
+        self.shape = (batch, dim) + tuple(reversed(self.n))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sem_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind(self):
+        _call(lib().sem_set_stream(self._h, _stream()))
+
+    def _chk(self, t, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise SemError(f"{name} must be a CUDA tensor")
+        if t.dtype != self.dtype:
+            raise SemError(f"{name} has dtype {t.dtype}, context uses {self.dtype}")
+        if not t.is_contiguous():
+            raise SemError(f"{name} must be contiguous")
+        if t.numel() != self.batch * self.ndof:
+            raise SemError(f"{name} has {t.numel()} values, expected {self.batch * self.ndof}")
+        return t
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=self.dtype, device="cuda")
+
+    def node_coords(self, k):
+        x = np.zeros(self.n[k])
+        _call(lib().sem_node_coords(self._h, k, x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return x
+
+    def rhs(self, u, out=None):
+        self._chk(u, "u")
+        out = self.empty() if out is None else self._chk(out, "out")
+        self._bind()
+        _call(lib().sem_rhs(self._h, _ptr(u), _ptr(out)))
+        return out
+
+    def jac_vec(self, u, v, out=None):
+        self._chk(u, "u"), self._chk(v, "v")
+        out = self.empty() if out is None else self._chk(out, "out")
+        self._bind()
+        _call(lib().sem_jac_vec(self._h, _ptr(u), _ptr(v), _ptr(out)))
+        return out
+
+    def jact_vec(self, u, w, out=None):
+        self._chk(u, "u"), self._chk(w, "w")
+        out = self.empty() if out is None else self._chk(out, "out")
+        self._bind()
+        _call(lib().sem_jact_vec(self._h, _ptr(u), _ptr(w), _ptr(out)))
+        return out
+
+    def set_check_finite(self, on=True):
+        _call(lib().sem_set_check_finite(self._h, 1 if on else 0))
+
+    def rk4_forward(self, u0, dt, nsteps, ckpt_every=0, inplace=False):
+        """Returns (u(T), checkpoints [nsteps/K][batch][C][...] or None)."""
+        self._chk(u0, "u0")
+        u = u0 if inplace else u0.clone()
+        ck = None
+        if ckpt_every:
+            ck = torch.empty((nsteps // ckpt_every,) + self.shape, dtype=self.dtype, device="cuda")
+        self._bind()
+        _call(lib().sem_rk4_forward(self._h, _ptr(u), float(dt), int(nsteps), int(ckpt_every),
+                                    _ptr(ck) if ck is not None else None))
+        return u, ck
+
+    def workspace_bytes(self, ckpt_every):
+        b = _i64()
+        _call(lib().sem_workspace_bytes(self._h, int(ckpt_every), ctypes.byref(b)))
+        return b.value
+
+    def rk4_adjoint(self, ckpt, dt, nsteps, ckpt_every, lamT, work=None):
+        """lambda_0 = dPhi/du_0 from lambda_N = dPhi/du(T) (discrete RK4 adjoint)."""
+        self._chk(lamT, "lamT")
+        if not ckpt.is_contiguous() or ckpt.dtype != self.dtype:
+            raise SemError("ckpt must be a contiguous tensor of the context dtype")
+        if ckpt.numel() != (nsteps // ckpt_every) * self.batch * self.ndof:
+            raise SemError("ckpt has the wrong size")
+        lam = lamT.clone()
+        if work is None:
+            nbytes = self.workspace_bytes(ckpt_every)
+            work = torch.empty(nbytes // (8 if self.dtype == torch.float64 else 4), dtype=self.dtype, device="cuda")
+        self._bind()
+        _call(lib().sem_rk4_adjoint(self._h, _ptr(ckpt), float(dt), int(nsteps), int(ckpt_every), _ptr(lam),
+                                    _ptr(work)))
+        return lam
+
+
+class SEMRhs(torch.autograd.Function):
+    """f = F(u) with backward u_bar = J(u)^T f_bar (Sec. 3.3, eq. jactransvec)."""
+
+    @staticmethod
+    def forward(ctx, u, sem):
+        ctx.sem = sem
+        ctx.save_for_backward(u)
+        return sem.rhs(u.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        (u,) = ctx.saved_tensors
+        return ctx.sem.jact_vec(u.contiguous(), g.contiguous()), None
+
+
+class SEMTrajectory(torch.autograd.Function):
+    """u(T) = RK4^nsteps(u_0) with backward by the discrete RK4 adjoint (Sec. 4.1) from uniform
+    checkpoints every ckpt_every steps, recomputed segment by segment (Sec. 5.3)."""
+
+    @staticmethod
+    def forward(ctx, u0, sem, dt, nsteps, ckpt_every):
+        uT, ck = sem.rk4_forward(u0.contiguous(), dt, nsteps, ckpt_every)
+        ctx.sem, ctx.dt, ctx.nsteps, ctx.K = sem, dt, nsteps, ckpt_every
+        ctx.save_for_backward(ck)
+        return uT
+
+    @staticmethod
+    def backward(ctx, g):
+        (ck,) = ctx.saved_tensors
+        lam0 = ctx.sem.rk4_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous())
+        return lam0, None, None, None, None
+
+
+def trajectory(u0, sem, dt, nsteps, ckpt_every):
+    return SEMTrajectory.apply(u0, sem, dt, nsteps, ckpt_every)
+
+
+class Batch:
+    """Independent 2-D (or 1-D/3-D, shared dim) problems of uneven size/order packed back to back."""
+
+    def __init__(self, problems, dtype=torch.float64):
+        """problems: list of dicts with keys dim, order, elems, length, nu, dt."""
+        if not torch.cuda.is_available():
+            raise SemError("no GPU available: libsem runs only on the GPU")
+        self.problems = list(problems)
+        self.dtype = dtype
+        n = len(self.problems)
+        descs = (SemDesc * n)(*[_desc(p["dim"], p["order"], p["elems"], p["length"], p["nu"], dtype, 1)
+                                for p in self.problems])
+        dts = (ctypes.c_double * n)(*[float(p["dt"]) for p in self.problems])
+        self._h = _vp()
+        _call(lib().sem_batch_setup(descs, dts, n, _stream(), ctypes.byref(self._h)))
+        offs = (ctypes.c_int64 * (n + 1))()
+        _call(lib().sem_batch_query(self._h, offs))
+        self.offsets = [int(o) for o in offs]
+        self.total = self.offsets[-1]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().sem_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self):
+        return torch.empty(self.total, dtype=self.dtype, device="cuda")
+
+    def view(self, packed, p):
+        """Problem p's field [1][C][...] as a view of the packed array."""
+        q = self.problems[p]
+        n = [e * q["order"] for e in q["elems"]]
+        return packed[self.offsets[p]:self.offsets[p + 1]].view((1, q["dim"]) + tuple(reversed(n)))
+
+    def _chk(self, t, name):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous():
+            raise SemError(f"{name} must be a contiguous CUDA tensor of dtype {self.dtype}")
+        if t.numel() != self.total:
+            raise SemError(f"{name} has {t.numel()} values, expected {self.total}")
+        return t
+
+    def rhs(self, u, out=None):
+        self._chk(u, "u")
+        out = self.empty() if out is None else self._chk(out, "out")
+        _call(lib().sem_batch_rhs(self._h, _ptr(u), _ptr(out)))
+        return out
+
+    def jact_vec(self, u, w, out=None):
+        self._chk(u, "u"), self._chk(w, "w")
+        out = self.empty() if out is None else self._chk(out, "out")
+        _call(lib().sem_batch_jact_vec(self._h, _ptr(u), _ptr(w), _ptr(out)))
+        return out
+
+    def rk4_forward(self, u0, nsteps, ckpt_every=0):
+        self._chk(u0, "u0")
+        u = u0.clone()
+        ck = None
+        if ckpt_every:
+            ck = torch.empty((nsteps // ckpt_every, self.total), dtype=self.dtype, device="cuda")
+        _call(lib().sem_batch_rk4_forward(self._h, _ptr(u), int(nsteps), int(ckpt_every),
+                                          _ptr(ck) if ck is not None else None))
+        return u, ck
+
+    def rk4_adjoint(self, ckpt, nsteps, ckpt_every, lamT, work=None):
+        self._chk(lamT, "lamT")
+        lam = lamT.clone()
+        if work is None:
+            b = _i64()
+            _call(lib().sem_batch_workspace_bytes(self._h, int(ckpt_every), ctypes.byref(b)))
+            work = torch.empty(b.value // (8 if self.dtype == torch.float64 else 4), dtype=self.dtype, device="cuda")
+        _call(lib().sem_batch_rk4_adjoint(self._h, _ptr(ckpt), int(nsteps), int(ckpt_every), _ptr(lam), _ptr(work)))
+        return lam
+
+    def autotune(self):
+        ms = _f64()
+        _call(lib().sem_batch_autotune(self._h, ctypes.byref(ms)))
+        return ms.value

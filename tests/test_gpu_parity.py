@@ -1,0 +1,312 @@
+"""GPU parity: libsem (HIP, through its C ABI) against the CPU oracle, element by element.
+
+Tolerances: FP64 per operator application <= 1e-12 and after a trajectory <= 1e-10, both measured
+norm-wise as max|x - x_ref| / max|x_ref| (fields cross zero, so element-wise relative error is not
+meaningful).  FP32 results are compared with the FP64 oracle at 1e-4 (rounding of 8-point
+contractions in single precision, ~1e-6 expected).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL_APPLY = 1e-12
+TOL_TRAJ = 1e-10
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1806_01422_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return P
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = a.detach().cpu().double().numpy() if isinstance(a, torch.Tensor) else a
+    b = b.detach().cpu().double().numpy() if isinstance(b, torch.Tensor) else b
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def gpu(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def make(P, dim, N, E, nu=0.01, batch=1, L=None, dtype=torch.float64):
+    L = list(L or [1.0] * dim)
+    m = oracle.Mesh(dim, N, list(E), L, nu, batch)
+    c = P.Context(dim, N, list(E), L, nu, dtype=dtype, batch=batch)
+    assert c.shape == m.shape
+    return m, c
+
+
+def fields(m, seed):
+    xs = [m.coords(k) for k in range(m.dim)]
+    u = np.stack([wl.fourier_field(xs, m.L[: m.dim], 3, seed + b) for b in range(m.batch)])
+    v = wl.normal_field(m.shape, seed + 100)
+    w = wl.normal_field(m.shape, seed + 200)
+    return u, v, w
+
+
+CASES = [
+    (1, 8, [16]), (1, 1, [3]), (1, 12, [5]), (1, 3, [1]), (1, 5, [37]),
+    (2, 7, [5, 3]), (2, 1, [2, 2]), (2, 2, [2, 2]), (2, 12, [3, 2]), (2, 5, [1, 4]), (2, 9, [7, 5]),
+    (2, 6, [3, 3]),
+    (3, 7, [3, 2, 4]), (3, 1, [2, 2, 2]), (3, 9, [2, 3, 2]), (3, 4, [1, 2, 3]), (3, 2, [5, 1, 1]),
+    (3, 7, [1, 1, 1]), (3, 5, [3, 3, 3]),
+]
+
+
+@pytest.mark.parametrize("dim,N,E", CASES)
+def test_operators_fp64(P, dim, N, E):
+    note(f"operators fp64 dim={dim} N={N} E={E}")
+    m, c = make(P, dim, N, E, nu=0.02)
+    u, v, w = fields(m, 7)
+    U, V, W = gpu(u), gpu(v), gpu(w)
+    assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
+    assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < TOL_APPLY
+    assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < TOL_APPLY
+
+
+@pytest.mark.parametrize("dim,N,E", [(1, 8, [16]), (2, 7, [5, 3]), (3, 7, [3, 2, 4]), (3, 5, [2, 2, 3])])
+def test_operators_fp32(P, dim, N, E):
+    note(f"operators fp32 dim={dim} N={N} E={E}")
+    m, c = make(P, dim, N, E, nu=0.02, dtype=torch.float32)
+    u, v, w = fields(m, 9)
+    U, V, W = gpu(u, torch.float32), gpu(v, torch.float32), gpu(w, torch.float32)
+    assert rel(c.rhs(U), m.rhs(u)) < 1e-4
+    assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < 1e-4
+    assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < 1e-4
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_batched_fields(P, dim):
+    note(f"same-shape batch dim={dim}")
+    m, c = make(P, dim, 4, [3, 2, 2][:dim], nu=0.03, batch=3)
+    u, v, w = fields(m, 11)
+    U, V, W = gpu(u), gpu(v), gpu(w)
+    assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
+    assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < TOL_APPLY
+    assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < TOL_APPLY
+
+
+def test_dot_identity_gpu(P):
+    note("dot identity on the GPU, 3-D N=7")
+    m, c = make(P, 3, 7, [3, 3, 2], nu=0.01)
+    u, v, w = fields(m, 13)
+    U, V, W = gpu(u), gpu(v), gpu(w)
+    lhs = torch.dot(c.jac_vec(U, V).flatten(), W.flatten()).item()
+    rhs = torch.dot(V.flatten(), c.jact_vec(U, W).flatten()).item()
+    scale = (c.jac_vec(U, V).norm() * W.norm()).item()
+    assert abs(lhs - rhs) < 1e-13 * scale
+
+
+# ------------------------------------------------------------------------------------------------
+# Full-size configurations (the shapes the benchmark times)
+# ------------------------------------------------------------------------------------------------
+def test_full_size_2d(P):
+    cfg = wl.C2
+    note("full-size 2-D 64x64 N=7 F, Jv, J^T")
+    m, c = make(P, 2, cfg.N, cfg.E, nu=cfg.nu, L=cfg.L)
+    xs = [m.coords(k) for k in range(2)]
+    u = wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C2_SEEDS["u"])[None]
+    v = wl.normal_field(m.shape, wl.C2_SEEDS["v"])
+    w = wl.normal_field(m.shape, wl.C2_SEEDS["w"])
+    U, V, W = gpu(u), gpu(v), gpu(w)
+    assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
+    assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < TOL_APPLY
+    assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < TOL_APPLY
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_full_size_3d(P, dtype):
+    cfg = wl.C3
+    note(f"full-size 3-D 32^3 N=7 F, Jv, J^T {dtype}")
+    m = oracle.Mesh(3, cfg.N, list(cfg.E), list(cfg.L), cfg.nu)
+    c = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=dtype)
+    xs = [m.coords(k) for k in range(3)]
+    u = wl.fourier_field(xs, cfg.L, wl.C3_K, wl.C3_SEEDS["u"])[None]
+    w = wl.normal_field(m.shape, wl.C3_SEEDS["w"])
+    v = wl.normal_field(m.shape, wl.C3_SEEDS["v"])
+    tol = TOL_APPLY if dtype == torch.float64 else 1e-4
+    U, V, W = gpu(u, dtype), gpu(v, dtype), gpu(w, dtype)
+    ef = rel(c.rhs(U), m.rhs(u))
+    ej = rel(c.jact_vec(U, W), m.jact_vec(u, w))
+    ev = rel(c.jac_vec(U, V), m.jac_vec(u, v))
+    note(f"  errors F {ef:.3e}  J^T {ej:.3e}  Jv {ev:.3e}")
+    assert ef < tol and ej < tol and ev < tol
+
+
+# ------------------------------------------------------------------------------------------------
+# RK4 trajectories, adjoint and autograd
+# ------------------------------------------------------------------------------------------------
+def c1_inputs():
+    m = oracle.Mesh(1, wl.C1.N, list(wl.C1.E), list(wl.C1.L), wl.C1.nu)
+    x = m.coords(0)
+    loc1 = wl.normal_field((1, m.nelem, 1, m.nloc), wl.C1_SEEDS["ic"])
+    loc2 = wl.normal_field((1, m.nelem, 1, m.nloc), wl.C1_SEEDS["target"])
+    u0 = np.sin(x)[None, None] + 0.01 * m.project_local(loc1)
+    up = np.sin(x)[None, None] + 0.01 * m.project_local(loc2)
+    target, _ = m.rk4_forward(up, wl.C1_DT, wl.C1_STEPS)
+    return m, u0, target
+
+
+def test_c1_trajectory_and_gradient(P):
+    note("C1: 1-D RK4 100 steps, adjoint gradient, autograd")
+    m, u0, target = c1_inputs()
+    c = P.Context(1, wl.C1.N, wl.C1.E, wl.C1.L, wl.C1.nu)
+    dt, n, K = wl.C1_DT, wl.C1_STEPS, 10
+    uT_ref, _ = m.rk4_forward(u0, dt, n)
+    uT, _ = c.rk4_forward(gpu(u0), dt, n)
+    assert rel(uT, uT_ref) < TOL_TRAJ
+    phi_ref, g_ref = m.gradient(u0, target, dt, n, K)
+    x = gpu(u0).requires_grad_(True)
+    yT = P.trajectory(x, c, dt, n, K)
+    loss = 0.5 * ((yT - gpu(target)) ** 2).sum()
+    loss.backward()
+    assert abs(loss.item() - phi_ref[0]) < 1e-12 * abs(phi_ref[0])
+    assert rel(x.grad, g_ref) < TOL_TRAJ
+    # central finite differences of the GPU trajectory on 16 random directions
+    def Phi(uu):
+        yy, _ = c.rk4_forward(gpu(uu), dt, n)
+        return 0.5 * ((yy - gpu(target)) ** 2).sum().item()
+    g = x.grad.cpu().numpy()
+    for s in range(16):
+        d = wl.normal_field(m.shape, 300 + s)
+        eps = 1e-4 * np.linalg.norm(u0) / np.linalg.norm(d)
+        fd = (8 * (Phi(u0 + eps * d) - Phi(u0 - eps * d)) - (Phi(u0 + 2 * eps * d) - Phi(u0 - 2 * eps * d))) / (
+            12 * eps)
+        ad = float(np.vdot(g, d))
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (s, fd, ad)
+
+
+@pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1)])
+def test_rk4_forward_adjoint(P, dim, N, E, batch):
+    note(f"RK4 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    u, _, w = fields(m, 17)
+    dt, n, K = 2e-3, 20, 5
+    uT_ref, ck_ref = m.rk4_forward(u, dt, n, K)
+    uT, ck = c.rk4_forward(gpu(u), dt, n, K)
+    assert rel(uT, uT_ref) < TOL_TRAJ
+    assert rel(ck, ck_ref) < TOL_TRAJ
+    lam_ref = m.rk4_adjoint(ck_ref, dt, n, K, w)
+    lam = c.rk4_adjoint(ck, dt, n, K, gpu(w))
+    assert rel(lam, lam_ref) < TOL_TRAJ
+
+
+def test_c4_shape_batch_gradient(P):
+    # the 64-IC 2-D configuration at full mesh size; a 50-step horizon keeps the oracle side short.
+    cfg = wl.C4
+    note("C4 shape: 64 ICs on 64x64 N=7, 50 steps, K=10 (oracle on ICs 0 and 63)")
+    dt, n, K = wl.C4_DT, 50, 10
+    c = P.Context(2, cfg.N, cfg.E, cfg.L, cfg.nu, batch=cfg.batch)
+    m1 = oracle.Mesh(2, cfg.N, list(cfg.E), list(cfg.L), cfg.nu, 1)
+    xs = [m1.coords(k) for k in range(2)]
+    u0 = np.stack([wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C4_IC_SEED0 + b) for b in range(cfg.batch)])
+    tg = np.stack([wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C4_TARGET_SEED0 + b) for b in range(cfg.batch)])
+    x = gpu(u0).requires_grad_(True)
+    yT = P.trajectory(x, c, dt, n, K)
+    loss = 0.5 * ((yT - gpu(tg)) ** 2).sum()
+    loss.backward()
+    for b in (0, cfg.batch - 1):
+        phi, g = m1.gradient(u0[b:b + 1], tg[b:b + 1], dt, n, K)
+        assert rel(x.grad[b:b + 1], g) < TOL_TRAJ, b
+
+
+# ------------------------------------------------------------------------------------------------
+# Batched uneven problems
+# ------------------------------------------------------------------------------------------------
+def batch_problems(count):
+    probs = wl.c5_problems(count)
+    return [dict(dim=2, order=p.N, elems=(p.E, p.E), length=(1.0, 1.0), nu=p.nu, dt=p.dt) for p in probs], probs
+
+
+def test_batch_operators_match_single(P):
+    note("batched uneven set (C5 recipe, 24 problems): F and J^T vs per-problem and oracle")
+    specs, probs = batch_problems(24)
+    B = P.Batch(specs)
+    u = B.empty()
+    w = B.empty()
+    for i, (s, p) in enumerate(zip(specs, probs)):
+        m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
+        xs = [m.coords(k) for k in range(2)]
+        B.view(u, i).copy_(gpu(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]))
+        B.view(w, i).copy_(gpu(wl.normal_field(m.shape, p.target_seed)))
+    f = B.rhs(u)
+    jt = B.jact_vec(u, w)
+    for i, s in enumerate(specs):
+        c = P.Context(2, s["order"], s["elems"], s["length"], s["nu"])
+        ui, wi = B.view(u, i).contiguous(), B.view(w, i).contiguous()
+        assert torch.equal(B.view(f, i), c.rhs(ui)), i
+        assert torch.equal(B.view(jt, i), c.jact_vec(ui, wi)), i
+        if i % 6 == 0:
+            m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
+            assert rel(B.view(f, i), m.rhs(ui.cpu().numpy())) < TOL_APPLY
+            assert rel(B.view(jt, i), m.jact_vec(ui.cpu().numpy(), wi.cpu().numpy())) < TOL_APPLY
+
+
+def test_batch_trajectory_gradient(P):
+    note("batched uneven set (12 problems): RK4 forward + adjoint vs per-problem oracle")
+    specs, probs = batch_problems(12)
+    B = P.Batch(specs)
+    u = B.empty()
+    lam = B.empty()
+    for i, (s, p) in enumerate(zip(specs, probs)):
+        m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
+        xs = [m.coords(k) for k in range(2)]
+        B.view(u, i).copy_(gpu(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]))
+        B.view(lam, i).copy_(gpu(wl.normal_field(m.shape, p.target_seed)))
+    n, K = 12, 4
+    uT, ck = B.rk4_forward(u, n, K)
+    lam0 = B.rk4_adjoint(ck, n, K, lam)
+    for i, s in enumerate(specs):
+        if s["elems"][0] > 16:
+            continue  # keep the oracle side short
+        m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
+        ui = B.view(u, i).cpu().numpy()
+        ref, ckr = m.rk4_forward(ui, s["dt"], n, K)
+        assert rel(B.view(uT, i), ref) < TOL_TRAJ, i
+        lr = m.rk4_adjoint(ckr, s["dt"], n, K, B.view(lam, i).cpu().numpy())
+        assert rel(B.view(lam0, i), lr) < TOL_TRAJ, i
+
+
+# ------------------------------------------------------------------------------------------------
+# Error handling at the boundary
+# ------------------------------------------------------------------------------------------------
+def test_errors(P):
+    note("argument errors")
+    with pytest.raises(P.SemError):
+        P.Context(3, 10, [2, 2, 2], [1, 1, 1], 0.1)  # order outside the compiled 3-D range
+    with pytest.raises(P.SemError):
+        P.Context(2, 3, [0, 2], [1, 1], 0.1)
+    m, c = make(P, 2, 3, [2, 2])
+    u = torch.zeros(c.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.SemError):
+        P.lib() and P.sem._call(P.lib().sem_rhs(c._h, P.sem._ptr(u), P.sem._ptr(u)))  # aliasing
+    with pytest.raises(P.SemError):
+        c.rk4_forward(u, 1e-3, 10, 3)  # 3 does not divide 10
+    with pytest.raises(P.SemError):
+        c.rk4_forward(u, -1.0, 10, 0)
+    with pytest.raises(P.SemError):
+        c.rhs(torch.zeros(5, dtype=torch.float64, device="cuda"))
+
+
+def test_nonfinite_detection(P):
+    note("non-finite trajectory detection")
+    m, c = make(P, 1, 8, [16], nu=0.01, L=[2 * np.pi])
+    u = gpu(np.sin(m.coords(0))[None, None])
+    c.set_check_finite(True)
+    c.rk4_forward(u, 1e-3, 10)
+    with pytest.raises(P.SemError):
+        c.rk4_forward(u, 5.0, 200)  # far beyond the stability limit
