@@ -1,0 +1,241 @@
+"""Benchmark of the SEM Burgers hot path on one MI355X.
+
+Main timed step (the metric's workload): on the 3-D periodic unit cube with 32^3 hexahedral
+elements of order N = 7 (33,718,272 unique DOF, FP64), one step applies F(u) and J(u)^T w once each.
+`value` is DOF processed per second by that pair, in GDOF/s.  Per-operator GDOF/s (F, J v, J^T),
+the J^T/F cost ratio, the FP32 variant, adjoint gradients/s of the 64-IC 2-D configuration and the
+batched-vs-plain gradient/s of the 128 uneven 2-D problems are reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as wl  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E datasheet peak
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def event_time_ms(fn, reps):
+    """Average milliseconds per call of fn over reps calls, HIP events on the current stream."""
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def c3_inputs(ctx, dtype):
+    cfg = wl.C3
+    xs = [ctx.node_coords(k) for k in range(3)]
+    u = wl.fourier_field(xs, cfg.L, wl.C3_K, wl.C3_SEEDS["u"])[None]
+    w = wl.normal_field(ctx.shape, wl.C3_SEEDS["w"])
+    v = wl.normal_field(ctx.shape, wl.C3_SEEDS["v"])
+    cv = lambda a: torch.from_numpy(a).to(device="cuda", dtype=dtype)  # noqa: E731
+    return cv(u), cv(v), cv(w)
+
+
+def cpu_baseline(target_s=12.0):
+    """The CPU oracle (FP64, OpenMP) on the host cores: F and J^T on the full 3-D field."""
+    import oracle
+    cfg = wl.C3
+    m = oracle.Mesh(3, cfg.N, list(cfg.E), list(cfg.L), cfg.nu)
+    xs = [m.coords(k) for k in range(3)]
+    u = wl.fourier_field(xs, cfg.L, wl.C3_K, wl.C3_SEEDS["u"])[None]
+    w = wl.normal_field(m.shape, wl.C3_SEEDS["w"])
+    reps, t_total, t0 = 0, 0.0, time.time()
+    while t_total < target_s and reps < 20:
+        t = time.time()
+        m.rhs(u)
+        m.jact_vec(u, w)
+        t_total += time.time() - t
+        reps += 1
+    dof = m.ndof
+    return {"value": round(dof * reps / t_total / 1e9, 5), "unit": "GDOF/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} x (F + J^T) on the full 32^3 N=7 FP64 field ({dof} DOF), "
+                      f"{t_total:.1f} s total on {oracle.num_threads()} threads"}
+
+
+def gradient_c4(P, nsteps=wl.C4_STEPS, K=wl.C4_CKPT):
+    cfg = wl.C4
+    ctx = P.Context(2, cfg.N, cfg.E, cfg.L, cfg.nu, batch=cfg.batch)
+    xs = [ctx.node_coords(k) for k in range(2)]
+    u0 = np.stack([wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C4_IC_SEED0 + b) for b in range(cfg.batch)])
+    tg = np.stack([wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C4_TARGET_SEED0 + b) for b in range(cfg.batch)])
+    U0, TG = torch.from_numpy(u0).cuda(), torch.from_numpy(tg).cuda()
+
+    def grad():
+        x = U0.clone().requires_grad_(True)
+        yT = P.trajectory(x, ctx, wl.C4_DT, nsteps, K)
+        loss = 0.5 * ((yT - TG) ** 2).sum()
+        loss.backward()
+        return x.grad
+
+    grad()  # warm-up (graph capture, allocations)
+    ms = event_time_ms(grad, 1)
+    return cfg.batch / (ms / 1e3), ms
+
+
+def c5_sets(P):
+    probs = wl.c5_problems()
+    specs = [dict(dim=2, order=p.N, elems=(p.E, p.E), length=(1.0, 1.0), nu=p.nu, dt=p.dt) for p in probs]
+    return probs, specs
+
+
+def gradient_c5(P, nsteps=wl.C5_STEPS, K=50):
+    """One gradient-descent iteration (forward + adjoint gradient of all 128 problems), batched
+    (packed set, one launch per order class per stage, graph-captured steps) vs plain (one context
+    per problem, launched one after another).  Both paths run the same kernels, so the gradients
+    are identical."""
+    probs, specs = c5_sets(P)
+    B = P.Batch(specs)
+    u0 = B.empty()
+    tg = B.empty()
+    for i, p in enumerate(probs):
+        ctxi = P.Context(2, p.N, (p.E, p.E), (1.0, 1.0), p.nu)
+        xs = [ctxi.node_coords(k) for k in range(2)]
+        B.view(u0, i).copy_(torch.from_numpy(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]))
+        B.view(tg, i).copy_(torch.from_numpy(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.target_seed)[None]))
+        ctxi.close()
+
+    def batched():
+        uT, ck = B.rk4_forward(u0, nsteps, K)
+        return B.rk4_adjoint(ck, nsteps, K, uT - tg)
+
+    ctxs = [P.Context(2, p.N, (p.E, p.E), (1.0, 1.0), p.nu) for p in probs]
+    views = [(B.view(u0, i).contiguous(), B.view(tg, i).contiguous()) for i in range(len(probs))]
+
+    def plain():
+        out = []
+        for c, p, (ui, ti) in zip(ctxs, probs, views):
+            uT, ck = c.rk4_forward(ui, p.dt, nsteps, K)
+            out.append(c.rk4_adjoint(ck, p.dt, nsteps, K, uT - ti))
+        return out
+
+    gb = batched()
+    gp = plain()
+    diff = max(float((B.view(gb, i) - gp[i]).abs().max()) for i in range(len(probs)))
+    tb = event_time_ms(batched, 1)
+    tp = event_time_ms(plain, 1)
+    return {"batched_gradients_per_s": round(len(probs) / (tb / 1e3), 2),
+            "plain_gradients_per_s": round(len(probs) / (tp / 1e3), 2),
+            "batched_over_plain": round(tp / tb, 3), "max_abs_gradient_diff": diff,
+            "problems": len(probs), "steps": nsteps, "total_dof": int(B.total)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path runs on one MI355X, "
+              "with no sharding or collectives", file=sys.stderr)
+        sys.exit(2)
+    import paper_1806_01422_amd as P
+
+    cfg = wl.C3
+    ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
+    dof = ctx.ndof
+    U, V, W = c3_inputs(ctx, torch.float64)
+    F, JT, JV = ctx.empty(), ctx.empty(), ctx.empty()
+
+    def step():
+        ctx.rhs(U, F)
+        ctx.jact_vec(U, W, JT)
+
+    log(f"3-D 32^3 N=7 FP64: {dof} DOF; warmup {args.warmup}, steps {args.steps}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    s.record()
+    for _ in range(args.steps):
+        step()
+    e.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = s.elapsed_time(e) / args.steps
+    value = dof / (ms_step / 1e3) / 1e9  # DOF through F + J^T per second
+    log(f"step (F + J^T): {ms_step:.4f} ms  ({value:.2f} GDOF/s), wall {wall:.3f} s")
+
+    reps = max(args.steps, 20)
+    t_f = event_time_ms(lambda: ctx.rhs(U, F), reps)
+    t_jt = event_time_ms(lambda: ctx.jact_vec(U, W, JT), reps)
+    t_jv = event_time_ms(lambda: ctx.jac_vec(U, V, JV), reps)
+    bytes_jt = 24.0 * dof  # read u and w, write J^T w (FP64)
+    achieved = bytes_jt / (t_jt / 1e3) / 1e9
+    out = {
+        "metric": "GDOF/s for F(u) and J^T w (FP64), J^T/F cost ratio, gradient/s batched vs plain",
+        "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "3-D periodic viscous Burgers, unit cube, 32^3 hex elements, order N=7 "
+                               "(8 GLL points per direction), nu=1e-3; step = F(u) + J(u)^T w",
+                   "elements": [32, 32, 32], "order": 7, "dof": dof, "fields": "u: seeded Fourier |k|<=6, "
+                   "1/|k|^2 spectrum, max|u|=1; w, v: seeded N(0,1)"},
+        "f_gdofs": round(dof / t_f / 1e6, 3), "jt_gdofs": round(dof / t_jt / 1e6, 3),
+        "jv_gdofs": round(dof / t_jv / 1e6, 3), "jt_over_f": round(t_jt / t_f, 4),
+        "f_ms": round(t_f, 5), "jt_ms": round(t_jt, 5), "jv_ms": round(t_jv, 5),
+        "roofline": {"bound": "hbm", "kernel": "J^T w apply", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "f_hbm_frac": round(16.0 * dof / (t_f / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    ctx.close()
+    del U, V, W, F, JT, JV
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        c32 = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float32)
+        U32, _, W32 = c3_inputs(c32, torch.float32)
+        t_f32 = event_time_ms(lambda: c32.rhs(U32), reps)
+        t_jt32 = event_time_ms(lambda: c32.jact_vec(U32, W32), reps)
+        c64 = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
+        U64, _, W64 = c3_inputs(c64, torch.float64)
+        f64, j64 = c64.rhs(U64), c64.jact_vec(U64, W64)
+        e_f = float((c32.rhs(U32).double() - f64).abs().max() / f64.abs().max())
+        e_j = float((c32.jact_vec(U32, W32).double() - j64).abs().max() / j64.abs().max())
+        out["fp32"] = {"f_gdofs": round(dof / t_f32 / 1e6, 3), "jt_gdofs": round(dof / t_jt32 / 1e6, 3),
+                       "f_rel_err_vs_fp64": e_f, "jt_rel_err_vs_fp64": e_j}
+        c32.close(), c64.close()
+        del U32, W32, U64, W64, f64, j64
+        torch.cuda.empty_cache()
+        log("fp32 done")
+        gps, ms = gradient_c4(P)
+        out["c4_adjoint"] = {"gradients_per_s": round(gps, 3), "ms_per_batch_of_64": round(ms, 2),
+                             "steps": wl.C4_STEPS, "ckpt_every": wl.C4_CKPT,
+                             "workload": "2-D 64x64 N=7, 64 ICs, RK4 dt=2e-4, misfit gradient via autograd"}
+        torch.cuda.empty_cache()
+        log("c4 done")
+        out["c5_batched"] = gradient_c5(P)
+        log("c5 done")
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+        log("cpu baseline done")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,13 +1,621 @@
-// Tuned 3-D kernels (filled in once the generic path is parity-green).
+// Tuned 3-D kernels for order N = 7 (8 GLL points per direction) on gfx950.
+//
+// Work decomposition.  A workgroup of 4 wavefronts owns a 2 x 2 block of element rows in (y, z);
+// each wavefront owns one row and sweeps it along x, one element per step, its 64 lanes covering
+// the 8 x 8 lines of the element.  Every lane keeps whole element lines in registers in one of
+// three maps:
+//     z-map  lane = a + 8b, register c      (global loads: 8 lanes read 64 contiguous bytes)
+//     y-map  lane = a + 8c, register b
+//     x-map  lane = b + 8c, register a      (output, x-direction summation)
+// with (a, b, c) the element-local (x, y, z) GLL indices.  The element tile moves between maps
+// through an XOR-swizzled LDS tile.  The contraction with D along the register direction uses
+// the centro-antisymmetry of the GLL differentiation matrix (D_{N-i,N-j} = -D_ij): even/odd
+// halves of the line need 32 multiply-adds instead of 64 (Sec. 3.3 sum factorisation, one
+// direction at a time).
+//
+// Direct-stiffness summation.  Along x the last point (a = 7) of an element is the first point
+// (a = 0) of the next: it is carried in registers to the next step, and the periodic wrap is
+// closed after the sweep.  Between the four rows of a workgroup the y- and z-faces are added
+// through LDS.  Nodes on the workgroup's own lower y/z boundary planes receive contributions from
+// neighbouring workgroups: the kernel writes its partial sum there, neighbours write theirs to a
+// face buffer, and fast3d_fixup adds them, divides by the mass and applies the epilogue.
 #include "sem_internal.h"
 
 namespace sem {
+namespace {
 
-bool fast3d_supported(int, int) { return false; }
-int64_t fast3d_face_values(const ProbDev&) { return 0; }
-hipError_t launch_fast3d(const ProbDev&, int, const void*, const void*, void*, void*, const Epi&, Coef, const void*,
-                         hipStream_t) {
-  return hipErrorInvalidValue;
+constexpr int NQ = 7;       // order
+constexpr int FROWS = 29;   // face-buffer planes per workgroup: 15 (y-local 14) + 14 (z-local 14)
+constexpr int SROWS = 27;   // owned boundary rows per workgroup: 14 (y-local 0) + 13 (z-local 0)
+
+// The even/odd blocks of D are A[i][m] = (D_im - D_i,7-m)/2 and B[i][m] = (D_im + D_i,7-m)/2
+// (i, m < 4).  Centro-antisymmetry makes the blocks of D^T their transposes (A' = B^T, B' = A^T),
+// so one 32-entry table serves both contractions.
+template <typename T>
+struct FastTab {
+  T A[16], B[16];
+  T w[8];            // GLL weights
+  T imq[8];          // 1 / (assembled 1-D reference mass at local index q): 1/(2 w_0) at q = 0, 7
+};
+
+struct FastArgs {
+  int Ex, Ey, Ez, nx, ny, nz;
+  int NWy, NWz;  // workgroup grid
+  double hh[3], sc[3], nu;
+  int64_t nodes;  // per component
+  const ProbDev* prob;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Raw buffer accesses: a lane whose byte offset is out of range (OOB) stores nothing and loads 0,
+// so lane predicates become offsets and the store sequence stays free of branches (which keeps
+// the compiler's wait counts exact: loads and stores share one counter on this architecture).
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+constexpr uint32_t OOB = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, 0, 0);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+
+// swizzled LDS tile index of element-local point (a, b, c)
+__device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b ^ (c & 1)) << 3) + (a ^ b); }
+
+// y = D x (TR = false) or y = D^T x (TR = true) on one 8-point line, even/odd split:
+//   e_m = x_m + x_{7-m}, o_m = x_m - x_{7-m};  y_i = s_i + d_i, y_{7-i} = s_i - d_i  (i < 4)
+//   D:   s_i = sum_m A[i][m] o_m,  d_i = sum_m B[i][m] e_m
+//   D^T: s_i = sum_m B[m][i] o_m,  d_i = sum_m A[m][i] e_m
+template <bool TR, typename T>
+__device__ __forceinline__ void contract(const T (&x)[8], T (&y)[8], const FastTab<T>* __restrict__ tb) {
+  const T e0 = x[0] + x[7], e1 = x[1] + x[6], e2 = x[2] + x[5], e3 = x[3] + x[4];
+  const T o0 = x[0] - x[7], o1 = x[1] - x[6], o2 = x[2] - x[5], o3 = x[3] - x[4];
+  const T* __restrict__ A = tb->A;
+  const T* __restrict__ B = tb->B;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T s, d;
+    if constexpr (!TR) {
+      s = A[4 * i] * o0 + A[4 * i + 1] * o1 + A[4 * i + 2] * o2 + A[4 * i + 3] * o3;
+      d = B[4 * i] * e0 + B[4 * i + 1] * e1 + B[4 * i + 2] * e2 + B[4 * i + 3] * e3;
+    } else {
+      s = B[i] * o0 + B[4 + i] * o1 + B[8 + i] * o2 + B[12 + i] * o3;
+      d = A[i] * e0 + A[4 + i] * e1 + A[8 + i] * e2 + A[12 + i] * e3;
+    }
+    y[i] = s + d;
+    y[7 - i] = s - d;
+  }
+}
+
+// Contribution of direction j (the lane's register direction) to the element residual of every
+// component.  ldU(i, U) / ldV(i, V) fill the 8 register values of component i of the state and of
+// the direction (J v) or scaled adjoint input Z = M^{-1} w (J^T) in the current map; emit(i, P)
+// receives the contribution to component i.  om[s] is the quadrature weight at register s,
+// K1 = nu sc_j^2, K2 = sc_j (the 2/h_j of D on the physical element folded in).
+template <typename T, int OP, typename LU, typename LV, typename EM>
+__device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const T (&om)[8], T K1, T K2,
+                                            const FastTab<T>* __restrict__ tb, EM emit) {
+  T c1[8], cu[8];
+  {
+    T Uj[8];
+    ldU(j, Uj);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      c1[s] = K1 * om[s];
+      cu[s] = K2 * om[s] * Uj[s];
+    }
+  }
+  if constexpr (OP == OP_RHS) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T Ui[8], G[8], f[8], t[8];
+      ldU(i, Ui);
+      contract<false>(Ui, G, tb);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) f[s] = c1[s] * G[s];
+      contract<true>(f, t, tb);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) t[s] = -(t[s] + cu[s] * G[s]);
+      emit(i, t);
+    }
+  } else if constexpr (OP == OP_JAC) {
+    T cv[8];
+    {
+      T Vj[8];
+      ldV(j, Vj);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) cv[s] = K2 * om[s] * Vj[s];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T X[8], G[8], H[8], t[8];
+      ldU(i, X);
+      contract<false>(X, G, tb);
+      ldV(i, X);
+      contract<false>(X, H, tb);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) X[s] = c1[s] * H[s];
+      contract<true>(X, t, tb);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) t[s] = -(t[s] + cv[s] * G[s] + cu[s] * H[s]);
+      emit(i, t);
+    }
+  } else {  // OP_JACT: V holds Z = M^{-1} w
+    T acc[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[s] = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T X[8], G[8];
+      ldU(i, X);
+      contract<false>(X, G, tb);
+      ldV(i, X);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) acc[s] += X[s] * G[s];
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc[s] *= K2 * om[s];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      T Zl[8], H[8], t[8];
+      ldV(l, Zl);
+      contract<false>(Zl, H, tb);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) H[s] = c1[s] * H[s] + cu[s] * Zl[s];
+      contract<true>(H, t, tb);
+#pragma unroll
+      for (int s = 0; s < 8; ++s) t[s] = (l == j) ? -(t[s] + acc[s]) : -t[s];
+      emit(l, t);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T coef(const Coef& c, double dt) {
+  return (T)(c.c0 + c.cdt * dt);
+}
+
+// EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
+// 2 = additionally o2 = a2 x2 + b2 s.
+template <typename T, int OP, int EP>
+__global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
+                                                     const T* __restrict__ u, const T* __restrict__ v,
+                                                     T* __restrict__ face, Epi epi, Coef in_scale) {
+  constexpr bool HASV = OP != OP_RHS;
+  __shared__ T sU[4][3][512];
+  __shared__ T sV[4][HASV ? 3 : 1][HASV ? 512 : 1];
+  __shared__ T sQ[4][3][512];
+  __shared__ T sEy[2][3][64];
+  __shared__ T sEz[2][3][64];
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wy = wave & 1, wz = wave >> 1;
+  const int wg = blockIdx.x;
+  const int Y = wg % g.NWy, Z = wg / g.NWy;
+  const int ey = 2 * Y + wy, ez = 2 * Z + wz;
+  const int64_t bo = (int64_t)blockIdx.y * 3 * g.nodes;  // batch member offset
+  const T* __restrict__ ub = u + bo;
+  const T* __restrict__ vb = HASV ? v + bo : nullptr;
+  const uint32_t fbytes = (uint32_t)(3 * g.nodes * sizeof(T));  // one batch member, all components
+  const __amdgpu_buffer_rsrc_t r_o1 = brsrc(static_cast<T*>(epi.o1) + bo, fbytes);
+  const __amdgpu_buffer_rsrc_t r_x1 = brsrc(EP >= 1 ? static_cast<const T*>(epi.x1) + bo : u, EP >= 1 ? fbytes : 0);
+  const __amdgpu_buffer_rsrc_t r_o2 = brsrc(EP >= 2 ? static_cast<T*>(epi.o2) + bo : u, EP >= 2 ? fbytes : 0);
+  const __amdgpu_buffer_rsrc_t r_x2 = brsrc(EP >= 2 ? static_cast<const T*>(epi.x2) + bo : u, EP >= 2 ? fbytes : 0);
+  const __amdgpu_buffer_rsrc_t r_fb =
+      brsrc(face + ((int64_t)blockIdx.y * g.NWy * g.NWz + wg) * 3 * FROWS * g.nx,
+            (uint32_t)(3 * FROWS * g.nx * sizeof(T)));
+  const double dt = g.prob->dt;
+  const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
+
+  const int l0 = lane & 7, l1 = lane >> 3;
+  const T ihhh = (T)(1.0 / (g.hh[0] * g.hh[1] * g.hh[2]));
+  // quadrature weight omega = (h_x h_y h_z / 8) w_a w_b w_c; with the lane holding the two fixed
+  // indices (l0, l1) and the register the third, the same 8 values serve all three maps
+  T om[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) om[s] = (T)(g.hh[0] * g.hh[1] * g.hh[2]) * tb->w[l0] * tb->w[l1] * tb->w[s];
+  const T K1x = (T)(g.nu * g.sc[0] * g.sc[0]), K1y = (T)(g.nu * g.sc[1] * g.sc[1]), K1z = (T)(g.nu * g.sc[2] * g.sc[2]);
+  const T K2x = (T)g.sc[0], K2y = (T)g.sc[1], K2z = (T)g.sc[2];
+  // inverse assembled mass, lane factor: (b=l0, c=l1) in the x-map, (a=l0, b=l1) in the z-map
+  const T mlane = tb->imq[l0] * tb->imq[l1] * ihhh;
+  const T zin = (T)(in_scale.c0 + in_scale.cdt * dt) * mlane;  // J^T input: scale * M^{-1} w
+
+  // z-map global addressing: lane (a=l0, b=l1), register c
+  const int64_t rowy = (int64_t)((7 * ey + l1) % g.ny) * g.nx;
+  int64_t zoff[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) zoff[c] = (int64_t)((7 * ez + c) % g.nz) * g.ny * g.nx + rowy;
+  // Output in the z-map: lane (a=l0, b=l1), register c, node (7ex + a, 7ey + b, 7ez + c).  The node
+  // is owned by this row when a, b, c < 7; it lies on the workgroup's lower y/z boundary planes
+  // (partial sum, completed later) when (wy == 0 && b == 0) or (wz == 0 && c == 0); the upper
+  // planes (wy == 1 && b == 7, wz == 1 && c == 7) go to the face buffer.
+  const bool xown = l0 < 7;
+  const int64_t orowz = ((int64_t)(7 * ey + l1) % g.ny) * g.nx;  // y row of the lane (b < 7: no wrap)
+  auto zrow = [&](int c) { return (int64_t)(7 * ez + c) * g.ny * g.nx; };  // c < 7 only
+  // face-buffer plane of (b = l1, c), -1 if none
+  auto fplane_of = [&](int c) -> int {
+    if (wy == 1 && l1 == 7 && !(wz == 0 && c == 7)) return 7 * wz + c;  // y-local 14, z-local 7wz+c
+    if (wz == 1 && c == 7 && l1 < 7) return 15 + 7 * wy + l1;           // z-local 14, y-local 7wy+b
+    return -1;
+  };
+
+  auto load_z = [&](int ex, T (&UU)[3][8], T (&VV)[3][8]) {
+    const int gx = (7 * ex + l0) % g.nx;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        UU[i][c] = ub[i * g.nodes + zoff[c] + gx];
+        if constexpr (HASV) VV[i][c] = vb[i * g.nodes + zoff[c] + gx];
+      }
+  };
+
+  // Write element ex from the z-map values Z[i][c] (read back from LDS after the x-map summation):
+  // finished nodes get M^{-1} and the epilogue, nodes on the workgroup's lower boundary planes the
+  // partial sum, the upper planes go to the face buffer.  a_lo excludes the x-plane a = 0 of element
+  // 0 until the periodic wrap is added.  Every lane issues the same stores; inactive ones drop.
+  auto emit = [&](int ex, const T (&Zv)[3][8], int a_lo, int a_hi, const T (&E1)[3][7], const T (&E2)[3][7]) {
+    const bool ina = xown && l0 >= a_lo && l0 < a_hi;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const T r = Zv[i][c];
+        if (c < 7) {
+          const bool own = ina && l1 < 7;
+          const bool surf = (wy == 0 && l1 == 0) || (wz == 0 && c == 0);
+          const uint32_t no = (uint32_t)((i * g.nodes + zrow(c) + orowz + 7 * ex + l0) * sizeof(T));
+          const T sm = (OP != OP_JACT) ? r * (mlane * tb->imq[c]) : r;
+          T r1 = b1 * sm;
+          if (EP >= 1) r1 += a1 * E1[i][c];
+          bstore(r_o1, own ? no : OOB, surf ? r : r1);
+          if (EP >= 2) bstore(r_o2, (own && !surf) ? no : OOB, a2 * E2[i][c] + b2 * sm);
+        }
+        const int fp = fplane_of(c);
+        if (wy == 1 || wz == 1) {  // waves without face-buffer planes skip these stores entirely
+          bstore(r_fb, (ina && fp >= 0) ? (uint32_t)(((i * FROWS + fp) * g.nx + 7 * ex + l0) * sizeof(T)) : OOB, r);
+        }
+      }
+  };
+
+  auto load_epi = [&](int ex, T (&E1)[3][7], T (&E2)[3][7], int a_lo, int a_hi) {
+    const bool ina = xown && l0 >= a_lo && l0 < a_hi && l1 < 7;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) {
+        const bool surf = (wy == 0 && l1 == 0) || (wz == 0 && c == 0);
+        const uint32_t no =
+            (ina && !surf) ? (uint32_t)((i * g.nodes + zrow(c) + orowz + 7 * ex + l0) * sizeof(T)) : OOB;
+        E1[i][c] = (EP >= 1) ? bload<T>(r_x1, no) : (T)0;
+        E2[i][c] = (EP >= 2) ? bload<T>(r_x2, no) : (T)0;
+      }
+  };
+
+  // x-map registers -> LDS tile -> z-map registers (after the summations along x, y, z)
+  auto to_zmap = [&](const T (&R)[3][8], T (&Zv)[3][8], T* __restrict__ tile) {
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) tile[i * 512 + tix(a, l0, l1)] = R[i][a];
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) Zv[i][c] = tile[i * 512 + tix(l0, l1, c)];
+    wave_sync();
+  };
+
+  // y then z exchange of the shared faces inside the workgroup (x-map registers [0, na))
+  auto exchange = [&](T (&R)[3][8], int na) {
+    if (wy == 0 && l0 == 7) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < 7; ++a)
+          if (a < na) sEy[wz][i][l1 * 8 + a] = R[i][a];
+    }
+    __syncthreads();
+    if (wy == 1 && l0 == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < 7; ++a)
+          if (a < na) R[i][a] += sEy[wz][i][l1 * 8 + a];
+    }
+    if (wz == 0 && l1 == 7) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < 7; ++a)
+          if (a < na) sEz[wy][i][l0 * 8 + a] = R[i][a];
+    }
+    __syncthreads();
+    if (wz == 1 && l1 == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int a = 0; a < 7; ++a)
+          if (a < na) R[i][a] += sEz[wy][i][l0 * 8 + a];
+    }
+  };
+
+  T* __restrict__ tU = sU[wave][0];
+  T* __restrict__ tQ = sQ[wave][0];
+  T* __restrict__ tV = HASV ? sV[wave][0] : sU[wave][0];
+  T cu[3][8], cv[3][8];
+  load_z(0, cu, cv);
+  T carry[3] = {0, 0, 0}, first0[3] = {0, 0, 0};
+
+  for (int ex = 0; ex < g.Ex; ++ex) {
+    // ---- z-map (lane (a=l0, b=l1), register c): stage the element tile, z-direction part
+    if constexpr (OP == OP_JACT) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cv[i][c] *= zin * tb->imq[c];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        tU[i * 512 + tix(l0, l1, c)] = cu[i][c];
+        if constexpr (HASV) tV[i * 512 + tix(l0, l1, c)] = cv[i][c];
+      }
+    map_contrib<T, OP>(
+        2,
+        [&](int i, T (&X)[8]) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) X[c] = cu[i][c];
+        },
+        [&](int i, T (&X)[8]) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) X[c] = cv[i][c];
+        },
+        om, K1z, K2z, tb,
+        [&](int i, const T (&P)[8]) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) tQ[i * 512 + tix(l0, l1, c)] = P[c];
+        });
+    // the z-map lines are no longer needed: prefetch the next element into the same registers
+    // (unconditionally: the last step reloads element 0, so the memory-op sequence is fixed)
+    load_z(ex + 1 < g.Ex ? ex + 1 : 0, cu, cv);
+    wave_sync();
+    // ---- y-map (lane (a=l0, c=l1), register b)
+    map_contrib<T, OP>(
+        1,
+        [&](int i, T (&X)[8]) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) X[b] = tU[i * 512 + tix(l0, b, l1)];
+        },
+        [&](int i, T (&X)[8]) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) X[b] = tV[i * 512 + tix(l0, b, l1)];
+        },
+        om, K1y, K2y, tb,
+        [&](int i, const T (&P)[8]) {
+          // read the 8 values first, then write: one LDS round trip per component instead of
+          // one per value (the compiler cannot prove the swizzled addresses distinct)
+          T q[8];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) q[b] = tQ[i * 512 + tix(l0, b, l1)];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) tQ[i * 512 + tix(l0, b, l1)] = q[b] + P[b];
+        });
+    wave_sync();
+    // ---- x-map (lane (b=l0, c=l1), register a)
+    T R[3][8];
+    map_contrib<T, OP>(
+        0,
+        [&](int i, T (&X)[8]) {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) X[a] = tU[i * 512 + tix(a, l0, l1)];
+        },
+        [&](int i, T (&X)[8]) {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) X[a] = tV[i * 512 + tix(a, l0, l1)];
+        },
+        om, K1x, K2x, tb,
+        [&](int i, const T (&P)[8]) {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) R[i][a] = P[a] + tQ[i * 512 + tix(a, l0, l1)];
+        });
+    // ---- x-direction summation: carry the shared face to the next element
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      R[i][0] += carry[i];
+      carry[i] = R[i][7];
+    }
+    exchange(R, 7);
+    if (ex == 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) first0[i] = R[i][0];
+    }
+    // ---- outputs, written from the z-map so that 8 lanes store one contiguous row segment
+    {
+      T Zv[3][8], E1[3][7], E2[3][7];
+      load_epi(ex, E1, E2, ex == 0 ? 1 : 0, 7);
+      to_zmap(R, Zv, tQ);
+      emit(ex, Zv, ex == 0 ? 1 : 0, 7, E1, E2);
+    }
+  }
+  // periodic wrap along x: the carried face of the last element belongs to the first element
+  {
+    T R[3][8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int a = 0; a < 8; ++a) R[i][a] = (a == 0) ? carry[i] : (T)0;
+    exchange(R, 1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) R[i][0] += first0[i];
+    T Zv[3][8], E1[3][7], E2[3][7];
+    load_epi(0, E1, E2, 0, 1);
+    to_zmap(R, Zv, tQ);
+    emit(0, Zv, 0, 1, E1, E2);
+  }
+}
+
+// Completes the nodes on each workgroup's lower y/z boundary planes: own partial (in o1) plus the
+// neighbours' face-buffer partials, inverse mass (F, J v) and epilogue.
+template <typename T, bool DIV>
+__global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>* __restrict__ tb,
+                                                    const T* __restrict__ face, Epi epi, int batch) {
+  const int NWG = g.NWy * g.NWz;
+  const int64_t total = (int64_t)batch * NWG * 3 * SROWS * g.nx;
+  int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= total) return;
+  const int x = (int)(t % g.nx);
+  t /= g.nx;
+  const int srow = (int)(t % SROWS);
+  t /= SROWS;
+  const int i = (int)(t % 3);
+  t /= 3;
+  const int wg = (int)(t % NWG);
+  const int b = (int)(t / NWG);
+  const int Y = wg % g.NWy, Z = wg / g.NWy;
+  const int yl = srow < 14 ? 0 : srow - 13;
+  const int zl = srow < 14 ? srow : 0;
+  const int gy = 14 * Y + yl, gz = 14 * Z + zl;
+  const int64_t bo = (int64_t)b * 3 * g.nodes;
+  const int64_t o = bo + i * g.nodes + ((int64_t)gz * g.ny + gy) * g.nx + x;
+  T* __restrict__ o1 = static_cast<T*>(epi.o1);
+  const int Ym = (Y - 1 + g.NWy) % g.NWy, Zm = (Z - 1 + g.NWz) % g.NWz;
+  auto fbv = [&](int W, int k) {
+    return face[(((int64_t)b * NWG + W) * 3 + i) * FROWS * g.nx + (int64_t)k * g.nx + x];
+  };
+  T s = o1[o];
+  if (yl == 0) s += fbv(Ym + g.NWy * Z, zl);
+  if (zl == 0) s += fbv(Y + g.NWy * Zm, 15 + yl);
+  if (yl == 0 && zl == 0) s += fbv(Ym + g.NWy * Zm, 14);
+  const double dt = g.prob->dt;
+  if (DIV) {
+    const int qx = x % NQ;  // local index within the element (0 on a shared face)
+    s *= tb->imq[qx] * tb->imq[yl % NQ] * tb->imq[zl % NQ] / (T)(g.hh[0] * g.hh[1] * g.hh[2]);
+  }
+  T r1 = coef<T>(epi.b1, dt) * s;
+  if (epi.x1) r1 += coef<T>(epi.a1, dt) * static_cast<const T*>(epi.x1)[o];
+  if (epi.o2) {
+    T r2 = coef<T>(epi.b2, dt) * s;
+    if (epi.x2) r2 += coef<T>(epi.a2, dt) * static_cast<const T*>(epi.x2)[o];
+    static_cast<T*>(epi.o2)[o] = r2;
+  }
+  o1[o] = r1;
+}
+
+template <typename T>
+void fill_tab(int N, FastTab<T>* t) {
+  double xi[MAXP], w[MAXP], D[MAXP * MAXP];
+  gll_tables(N, xi, w, D);
+  for (int i = 0; i < 4; ++i)
+    for (int m = 0; m < 4; ++m) {
+      const double dim = D[i * 8 + m], dimr = D[i * 8 + 7 - m];
+      t->A[4 * i + m] = (T)(0.5 * (dim - dimr));
+      t->B[4 * i + m] = (T)(0.5 * (dim + dimr));
+    }
+  for (int q = 0; q < 8; ++q) {
+    t->w[q] = (T)w[q];
+    t->imq[q] = (T)(1.0 / ((q == 0 || q == 7) ? 2.0 * w[0] : w[q]));
+  }
+}
+
+FastArgs make_args(const ProbDev& hp, const ProbDev* dprob) {
+  FastArgs g;
+  g.Ex = hp.E[0];
+  g.Ey = hp.E[1];
+  g.Ez = hp.E[2];
+  g.nx = hp.n[0];
+  g.ny = hp.n[1];
+  g.nz = hp.n[2];
+  g.NWy = hp.E[1] / 2;
+  g.NWz = hp.E[2] / 2;
+  for (int k = 0; k < 3; ++k) {
+    g.hh[k] = hp.hh[k];
+    g.sc[k] = hp.sc[k];
+  }
+  g.nu = hp.nu;
+  g.nodes = hp.nodes;
+  g.prob = dprob;
+  return g;
+}
+
+template <typename T>
+hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
+                    const Epi& epi, Coef in_scale, const void* dtab, hipStream_t s) {
+  const FastArgs g = make_args(hp, dprob);
+  const auto* tb = static_cast<const FastTab<T>*>(dtab);
+  const dim3 grid(g.NWy * g.NWz, hp.batch);
+  T* fc = static_cast<T*>(face);
+  const T* uu = static_cast<const T*>(u);
+  const T* vv = static_cast<const T*>(v);
+  const int ep = epi.o2 ? 2 : (epi.x1 ? 1 : 0);
+#define SEM_FAST_LAUNCH(OPV, EPV)                                                                           \
+  hipLaunchKernelGGL((fast3d_kernel<T, OPV, EPV>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale)
+#define SEM_FAST_EP(OPV)          \
+  if (ep == 0) SEM_FAST_LAUNCH(OPV, 0); \
+  else if (ep == 1) SEM_FAST_LAUNCH(OPV, 1); \
+  else SEM_FAST_LAUNCH(OPV, 2);
+  if (op == OP_RHS) {
+    SEM_FAST_EP(OP_RHS)
+  } else if (op == OP_JAC) {
+    SEM_FAST_EP(OP_JAC)
+  } else {
+    SEM_FAST_EP(OP_JACT)
+  }
+#undef SEM_FAST_EP
+#undef SEM_FAST_LAUNCH
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)hp.batch * g.NWy * g.NWz * 3 * SROWS * g.nx;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (op == OP_JACT)
+    hipLaunchKernelGGL((fast3d_fixup<T, false>), dim3(blocks), dim3(256), 0, s, g, tb, fc, epi, hp.batch);
+  else
+    hipLaunchKernelGGL((fast3d_fixup<T, true>), dim3(blocks), dim3(256), 0, s, g, tb, fc, epi, hp.batch);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fast3d_supported(const ProbDev& hp) {
+  // buffer offsets are 32-bit: one batch member (all components, FP64) must stay below 2 GiB
+  return hp.dim == 3 && hp.N == NQ && hp.E[1] % 2 == 0 && hp.E[2] % 2 == 0 && hp.E[0] >= 1 &&
+         (int64_t)3 * hp.nodes * 8 < ((int64_t)1 << 31);
+}
+
+int64_t fast3d_face_values(const ProbDev& hp) {
+  return (int64_t)hp.batch * (hp.E[1] / 2) * (hp.E[2] / 2) * 3 * FROWS * hp.n[0];
+}
+
+size_t fast3d_table_bytes() { return sizeof(FastTab<double>) + sizeof(FastTab<float>); }
+
+void fast3d_fill_tables(int N, void* host) {
+  fill_tab<double>(N, static_cast<FastTab<double>*>(host));
+  fill_tab<float>(N, reinterpret_cast<FastTab<float>*>(static_cast<char*>(host) + sizeof(FastTab<double>)));
+}
+
+hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
+                         const Epi& epi, Coef in_scale, const void* dtables, int dtype, hipStream_t s) {
+  if (dtype == SEM_F64) return run_fast<double>(hp, dprob, op, u, v, face, epi, in_scale, dtables, s);
+  return run_fast<float>(hp, dprob, op, u, v, face, epi, in_scale,
+                         static_cast<const char*>(dtables) + sizeof(FastTab<double>), s);
 }
 
 }  // namespace sem

@@ -186,7 +186,7 @@ struct OpSet {
   DevBuf lvec;
   bool fast = false;  // single 3-D problem handled by the tuned kernel
   DevBuf face;
-  DevTables fast_tab;
+  DevBuf fast_tab;
 
   int finalize() {
     int rc;
@@ -198,7 +198,8 @@ struct OpSet {
 
   hipError_t apply(int op, const void* u, const void* v, Coef in_scale, const Epi& epi, hipStream_t s) {
     if (fast)
-      return launch_fast3d(hp[0], op, u, v, epi.o1, face.p, epi, in_scale, fast_tab.get(dtype), s);
+      return launch_fast3d(hp[0], static_cast<const ProbDev*>(dprob.p), op, u, v, face.p, epi, in_scale, fast_tab.p,
+                           dtype, s);
     for (auto& c : classes) {
       ElemLaunch el{static_cast<const ProbDev*>(dprob.p) + c.first, c.count, c.nitems, dim, c.P, dtype, c.epb};
       hipError_t e = launch_elem(el, op, u, v, lvec.p, in_scale, c.tab.get(dtype), s);
@@ -223,7 +224,7 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     tmp[i].off = off[i];
   }
   os.total_vals = off[count];
-  os.fast = allow_fast && count == 1 && os.dim == 3 && descs[0].batch == 1 && fast3d_supported(descs[0].order, os.dtype);
+  os.fast = allow_fast && count == 1 && fast3d_supported(tmp[0]);
   // order classes
   std::vector<int> idx(count);
   for (int i = 0; i < count; ++i) idx[i] = i;
@@ -260,7 +261,10 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
   os.total_nodes = nodes0;
   if (os.fast) {
     int rc;
-    if ((rc = os.fast_tab.make(descs[0].order))) return rc;
+    std::vector<char> host(fast3d_table_bytes());
+    fast3d_fill_tables(descs[0].order, host.data());
+    if ((rc = os.fast_tab.alloc(host.size()))) return rc;
+    HIPCHK(hipMemcpy(os.fast_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
     if ((rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts))) return rc;
   }
   return os.finalize();

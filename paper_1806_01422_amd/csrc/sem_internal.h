@@ -77,10 +77,13 @@ int elem_epb_choices(int dim, int P, int* out, int max_out);
 // Host GLL tables in long double (gll.cpp)
 void gll_tables(int N, double* xi, double* w, double* D);
 
-// Fast 3-D path (kern_fast3d.hip): returns true if it handles (N, dtype).
-bool fast3d_supported(int N, int dtype);
-hipError_t launch_fast3d(const ProbDev& hp, int op, const void* u, const void* v, void* out, void* face,
-                         const Epi& epi, Coef in_scale, const void* tables, hipStream_t s);
-int64_t fast3d_face_values(const ProbDev& hp);
+// Tuned 3-D path for order 7 (kern_fast3d.hip).  The epilogue output o1 must alias none of the
+// operator inputs nor x1/x2 (it temporarily holds partial sums).
+bool fast3d_supported(const ProbDev& hp);
+int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch
+size_t fast3d_table_bytes();
+void fast3d_fill_tables(int N, void* host);  // fills fast3d_table_bytes() bytes
+hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
+                         const Epi& epi, Coef in_scale, const void* dtables, int dtype, hipStream_t s);
 
 }  // namespace sem

@@ -64,6 +64,8 @@ CASES = [
     (2, 6, [3, 3]),
     (3, 7, [3, 2, 4]), (3, 1, [2, 2, 2]), (3, 9, [2, 3, 2]), (3, 4, [1, 2, 3]), (3, 2, [5, 1, 1]),
     (3, 7, [1, 1, 1]), (3, 5, [3, 3, 3]),
+    # order 7 with even element counts in y and z runs the tuned 3-D kernel
+    (3, 7, [1, 2, 2]), (3, 7, [4, 4, 2]), (3, 7, [5, 2, 6]), (3, 7, [2, 6, 4]), (3, 7, [3, 4, 4]),
 ]
 
 
@@ -89,10 +91,10 @@ def test_operators_fp32(P, dim, N, E):
     assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < 1e-4
 
 
-@pytest.mark.parametrize("dim", [1, 2, 3])
-def test_batched_fields(P, dim):
-    note(f"same-shape batch dim={dim}")
-    m, c = make(P, dim, 4, [3, 2, 2][:dim], nu=0.03, batch=3)
+@pytest.mark.parametrize("dim,N", [(1, 4), (2, 4), (3, 4), (3, 7)])
+def test_batched_fields(P, dim, N):
+    note(f"same-shape batch dim={dim} N={N}")
+    m, c = make(P, dim, N, [3, 2, 2][:dim], nu=0.03, batch=3)
     u, v, w = fields(m, 11)
     U, V, W = gpu(u), gpu(v), gpu(w)
     assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
@@ -190,7 +192,8 @@ def test_c1_trajectory_and_gradient(P):
         assert abs(fd - ad) <= 1e-6 * abs(ad), (s, fd, ad)
 
 
-@pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1)])
+@pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1),
+                                           (3, 7, [3, 2, 4], 1), (3, 7, [2, 2, 2], 2)])
 def test_rk4_forward_adjoint(P, dim, N, E, batch):
     note(f"RK4 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
     m, c = make(P, dim, N, E, nu=0.01, batch=batch)
