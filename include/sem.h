@@ -135,9 +135,16 @@ int sem_batch_rk4_forward(sem_batch b, void* u, int32_t nsteps, int32_t ckpt_eve
 int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t ckpt_every, void* lam,
                           void* work);
 int sem_batch_workspace_bytes(sem_batch b, int32_t ckpt_every, int64_t* bytes);
-/* Time candidate launch shapes on the current inputs' sizes and keep the fastest (synchronises
-   the stream; results are cached per problem set).  best_ms (host, may be NULL) receives the
-   fastest RK4 step time. */
+/* Launch shape of the element stage.  persistent = 1: one persistent launch over all problems
+   (2-D sets of more than one problem) with `param` workgroups walking a cost-sorted work list;
+   persistent = 0: one launch per order class with `param` elements per workgroup (0 = default;
+   orders without that choice keep their default).  Drops the captured RK4 graphs (recaptured on
+   the next integration). */
+int sem_batch_configure(sem_batch b, int32_t persistent, int32_t param);
+/* Time the candidate launch shapes on the captured RK4 step of this problem set and keep the
+   fastest (synchronises the stream; overwrites the integrator's internal state buffers, not
+   caller data; results are cached per problem set for the process).  best_ms (host, may be NULL)
+   receives the fastest step time in milliseconds. */
 int sem_batch_autotune(sem_batch b, double* best_ms);
 
 #ifdef __cplusplus

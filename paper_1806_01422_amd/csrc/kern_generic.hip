@@ -63,25 +63,24 @@ __device__ inline T contract_t(const T* __restrict__ s, const T* __restrict__ D,
   return acc;
 }
 
+// Element residual of OP for the EPB elements of one workgroup.  Thread tid covers local point
+// q of element le = tid / P^DIM; `pr` / `loc` give that element's problem and its index among the
+// problem's batch-flattened elements (loc < 0: no element).  sD (P*P), sIn (EPB*NIN*C*NL) and
+// sT (EPB*C*DIM*NL) are LDS buffers.  Every thread of the workgroup must call this.
 template <typename T, int DIM, int P, int OP, int EPB>
-__global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* __restrict__ probs, int nprobs,
-                                                                  int64_t nitems, const Tables<T>* __restrict__ tab,
-                                                                  const T* __restrict__ u, const T* __restrict__ v,
-                                                                  T* __restrict__ L, Coef in_scale) {
+__device__ __forceinline__ void elem_body(int tid, const ProbDev* __restrict__ pr, int64_t loc,
+                                          const T* __restrict__ Dg, T* __restrict__ sD, T* __restrict__ sInb,
+                                          T* __restrict__ sTb, const T* __restrict__ u, const T* __restrict__ v,
+                                          T* __restrict__ L, Coef in_scale) {
   constexpr int NL = ipow(P, DIM);
   constexpr int C = DIM;
   constexpr int NIN = (OP == OP_RHS) ? 1 : 2;
-  __shared__ T sD[P * P];
-  __shared__ T sIn[EPB][NIN][C][NL];
-  __shared__ T sT[EPB][C][DIM][NL];
-
-  const int tid = threadIdx.x;
   const int le = tid / NL;
   const int q = tid - le * NL;
-  for (int i = tid; i < P * P; i += EPB * NL) sD[i] = tab->D[i];
-
-  const int64_t item = (int64_t)blockIdx.x * EPB + le;
-  const bool valid = item < nitems;
+  for (int i = tid; i < P * P; i += EPB * NL) sD[i] = Dg[i];
+  const bool valid = loc >= 0;
+  T* __restrict__ sIn = sInb + le * NIN * C * NL;  // [NIN][C][NL] of this element
+  T* __restrict__ sT = sTb + le * C * DIM * NL;    // [C][DIM][NL]
   int qd[3] = {0, 0, 0};
   {
     int t = q;
@@ -91,14 +90,12 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
       t /= P;
     }
   }
-  const ProbDev* pr = probs + (valid ? find_item(probs, nprobs, item) : 0);
 
   T U[C], V[C];
   T om = 0, nu = 0, sc[3] = {0, 0, 0};
   int64_t lbase = 0;
   if (valid) {
     const int N = pr->N;
-    const int64_t loc = item - pr->item0;
     const int64_t b = loc / pr->nelem;
     const int64_t e = loc - b * pr->nelem;
     int ed[3];
@@ -123,7 +120,7 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       U[c] = u[base + c * pr->nodes];
-      sIn[le][0][c][q] = U[c];
+      sIn[c * NL + q] = U[c];
     }
     if (OP != OP_RHS) {
       T s = 1;
@@ -131,7 +128,7 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         V[c] = v[base + c * pr->nodes] * s;
-        sIn[le][NIN - 1][c][q] = V[c];
+        sIn[((NIN - 1) * C + c) * NL + q] = V[c];
       }
     }
     lbase = pr->loff + loc * C * NL + q;
@@ -146,7 +143,7 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
         const int st = ipow(P, j);
-        G[i][j] = sc[j] * contract<T, P>(sIn[le][0][i], sD, qd[j], q - qd[j] * st, st);
+        G[i][j] = sc[j] * contract<T, P>(sIn + i * NL, sD, qd[j], q - qd[j] * st, st);
       }
     if (OP == OP_RHS) {
 #pragma unroll
@@ -154,7 +151,7 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
         T a = 0;
 #pragma unroll
         for (int j = 0; j < DIM; ++j) {
-          sT[le][i][j][q] = nu * om * G[i][j];
+          sT[(i * DIM + j) * NL + q] = nu * om * G[i][j];
           a += U[j] * G[i][j];
         }
         adv[i] = om * a;
@@ -166,7 +163,7 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
 #pragma unroll
         for (int j = 0; j < DIM; ++j) {
           const int st = ipow(P, j);
-          H[i][j] = sc[j] * contract<T, P>(sIn[le][1][i], sD, qd[j], q - qd[j] * st, st);
+          H[i][j] = sc[j] * contract<T, P>(sIn + (C + i) * NL, sD, qd[j], q - qd[j] * st, st);
         }
       if (OP == OP_JAC) {
 #pragma unroll
@@ -174,7 +171,7 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
           T a = 0;
 #pragma unroll
           for (int j = 0; j < DIM; ++j) {
-            sT[le][i][j][q] = nu * om * H[i][j];
+            sT[(i * DIM + j) * NL + q] = nu * om * H[i][j];
             a += V[j] * G[i][j] + U[j] * H[i][j];
           }
           adv[i] = om * a;
@@ -184,7 +181,7 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
         for (int l = 0; l < C; ++l) {
           T a = 0;
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) sT[le][l][j][q] = om * (nu * H[l][j] + U[j] * V[l]);
+          for (int j = 0; j < DIM; ++j) sT[(l * DIM + j) * NL + q] = om * (nu * H[l][j] + U[j] * V[l]);
 #pragma unroll
           for (int i = 0; i < C; ++i) a += V[i] * G[i][l];
           adv[l] = om * a;
@@ -200,10 +197,68 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
         const int st = ipow(P, j);
-        r += sc[j] * contract_t<T, P>(sT[le][i][j], sD, qd[j], q - qd[j] * st, st);
+        r += sc[j] * contract_t<T, P>(sT + (i * DIM + j) * NL, sD, qd[j], q - qd[j] * st, st);
       }
       L[lbase + i * NL] = -r - adv[i];
     }
+  }
+}
+
+template <typename T, int DIM, int P, int OP, int EPB>
+__global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* __restrict__ probs, int nprobs,
+                                                                  int64_t nitems, const Tables<T>* __restrict__ tab,
+                                                                  const T* __restrict__ u, const T* __restrict__ v,
+                                                                  T* __restrict__ L, Coef in_scale) {
+  constexpr int NL = ipow(P, DIM);
+  constexpr int NIN = (OP == OP_RHS) ? 1 : 2;
+  __shared__ T sD[P * P];
+  __shared__ T sIn[EPB * NIN * DIM * NL];
+  __shared__ T sT[EPB * DIM * DIM * NL];
+  const int tid = threadIdx.x;
+  const int64_t item = (int64_t)blockIdx.x * EPB + tid / NL;
+  const bool valid = item < nitems;
+  const ProbDev* pr = probs + (valid ? find_item(probs, nprobs, item) : 0);
+  elem_body<T, DIM, P, OP, EPB>(tid, pr, valid ? item - pr->item0 : -1, tab->D, sD, sIn, sT, u, v, L, in_scale);
+}
+
+// Persistent element kernel over a 2-D problem set of mixed orders: workgroup b processes work
+// items b, b + G, b + 2G, ... of a list sorted by decreasing cost; each item is up to NT / P^2
+// elements of one problem, dispatched on its order.  LDS is sized per thread, so one buffer fits
+// every order.
+template <typename T, int OP, int NT>
+__global__ __launch_bounds__(NT) void persist2d_kernel(const ProbDev* __restrict__ probs,
+                                                       const WorkItem* __restrict__ items, int nitems,
+                                                       const Tables<T>* __restrict__ tabs,
+                                                       const T* __restrict__ u, const T* __restrict__ v,
+                                                       T* __restrict__ L, Coef in_scale) {
+  constexpr int NIN = (OP == OP_RHS) ? 1 : 2;
+  __shared__ T sD[MAXP * MAXP];
+  __shared__ T sIn[NT * NIN * 2];
+  __shared__ T sT[NT * 4];
+  const int tid = threadIdx.x;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const WorkItem w = items[it];
+    const ProbDev* pr = probs + w.prob;
+    const int NL = w.P * w.P;
+    const int le = tid / NL;
+    const int64_t loc = (le < w.ne) ? w.e0 + le : -1;
+    const T* Dg = tabs[w.P].D;
+    switch (w.P) {
+#define SEM_PCASE(PV)                                                                                  \
+  case PV: {                                                                                           \
+    /* one uniform call: threads past the last whole element pass no element */                       \
+    constexpr int EPBV = NT / (PV * PV);                                                               \
+    const bool act = tid < EPBV * PV * PV;                                                             \
+    elem_body<T, 2, PV, OP, EPBV>(act ? tid : EPBV * PV * PV, pr, act ? loc : -1, Dg, sD, sIn, sT, u, v, \
+                                  L, in_scale);                                                        \
+    break;                                                                                             \
+  }
+      SEM_PCASE(2) SEM_PCASE(3) SEM_PCASE(4) SEM_PCASE(5) SEM_PCASE(6) SEM_PCASE(7) SEM_PCASE(8)
+      SEM_PCASE(9) SEM_PCASE(10) SEM_PCASE(11) SEM_PCASE(12) SEM_PCASE(13)
+#undef SEM_PCASE
+      default: break;
+    }
+    __syncthreads();  // the next item overwrites the LDS buffers
   }
 }
 
@@ -313,6 +368,44 @@ static hipError_t run_elem_epb(const ElemLaunch& el, const void* u, const void* 
     return run_elem<T, DIM, P, OP, DEF>(el, u, v, L, sc, tab, s);
   }
 }
+
+hipError_t launch_persist2d(const ProbDev* probs, const WorkItem* items, int nitems, int grid, int op, int dtype,
+                            const void* tabs, const void* u, const void* v, void* lvec, Coef in_scale, hipStream_t s) {
+  constexpr int NT = 256;
+  if (nitems <= 0) return hipSuccess;
+  if (dtype == SEM_F64) {
+    const auto* tb = static_cast<const Tables<double>*>(tabs);
+    const auto* uu = static_cast<const double*>(u);
+    const auto* vv = static_cast<const double*>(v);
+    auto* L = static_cast<double*>(lvec);
+    if (op == OP_RHS)
+      hipLaunchKernelGGL((persist2d_kernel<double, OP_RHS, NT>), dim3(grid), dim3(NT), 0, s, probs, items, nitems, tb, uu,
+                         vv, L, in_scale);
+    else if (op == OP_JAC)
+      hipLaunchKernelGGL((persist2d_kernel<double, OP_JAC, NT>), dim3(grid), dim3(NT), 0, s, probs, items, nitems, tb, uu,
+                         vv, L, in_scale);
+    else
+      hipLaunchKernelGGL((persist2d_kernel<double, OP_JACT, NT>), dim3(grid), dim3(NT), 0, s, probs, items, nitems, tb,
+                         uu, vv, L, in_scale);
+  } else {
+    const auto* tb = static_cast<const Tables<float>*>(tabs);
+    const auto* uu = static_cast<const float*>(u);
+    const auto* vv = static_cast<const float*>(v);
+    auto* L = static_cast<float*>(lvec);
+    if (op == OP_RHS)
+      hipLaunchKernelGGL((persist2d_kernel<float, OP_RHS, NT>), dim3(grid), dim3(NT), 0, s, probs, items, nitems, tb, uu,
+                         vv, L, in_scale);
+    else if (op == OP_JAC)
+      hipLaunchKernelGGL((persist2d_kernel<float, OP_JAC, NT>), dim3(grid), dim3(NT), 0, s, probs, items, nitems, tb, uu,
+                         vv, L, in_scale);
+    else
+      hipLaunchKernelGGL((persist2d_kernel<float, OP_JACT, NT>), dim3(grid), dim3(NT), 0, s, probs, items, nitems, tb,
+                         uu, vv, L, in_scale);
+  }
+  return hipGetLastError();
+}
+
+int persist2d_elems_per_item(int P) { return 256 / (P * P); }
 
 int elem_epb_choices(int dim, int P, int* out, int max_out) {
   int n = 0;

@@ -2,6 +2,8 @@
 // the batched uneven problem set.  Host code only; kernels live in kern_*.hip.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -187,6 +189,11 @@ struct OpSet {
   bool fast = false;  // single 3-D problem handled by the tuned kernel
   DevBuf face;
   DevBuf fast_tab;
+  // persistent mixed-order launch (2-D sets): cost-sorted work list and per-order tables
+  int persistent = 0;  // 0: one launch per order class, 1: one persistent launch
+  int pgrid = 1024;    // persistent grid size (workgroups)
+  DevBuf items, ptabs64, ptabs32;
+  int nitems = 0;
 
   int finalize() {
     int rc;
@@ -200,6 +207,14 @@ struct OpSet {
     if (fast)
       return launch_fast3d(hp[0], static_cast<const ProbDev*>(dprob.p), op, u, v, face.p, epi, in_scale, fast_tab.p,
                            dtype, s);
+    if (persistent && nitems > 0) {
+      hipError_t e = launch_persist2d(static_cast<const ProbDev*>(dprob.p), static_cast<const WorkItem*>(items.p), nitems,
+                                      pgrid, op, dtype, dtype == SEM_F64 ? ptabs64.p : ptabs32.p, u, v, lvec.p,
+                                      in_scale, s);
+      if (e != hipSuccess) return e;
+      return launch_dss(static_cast<const ProbDev*>(dprob.p), (int)hp.size(), total_nodes, dim, dtype, op != OP_JACT,
+                        lvec.p, epi, s);
+    }
     for (auto& c : classes) {
       ElemLaunch el{static_cast<const ProbDev*>(dprob.p) + c.first, c.count, c.nitems, dim, c.P, dtype, c.epb};
       hipError_t e = launch_elem(el, op, u, v, lvec.p, in_scale, c.tab.get(dtype), s);
@@ -258,6 +273,49 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
   }
   // item0 must be class-relative for element launches but node0 global: already so.
   os.lvals = lv;
+  if (os.dim == 2 && count > 1) {
+    // persistent work list: chunks of whole elements per 256-thread workgroup, largest cost first
+    struct It {
+      WorkItem w;
+      double cost;
+    };
+    std::vector<It> its;
+    for (size_t t = 0; t < os.hp.size(); ++t) {
+      const ProbDev& p = os.hp[t];
+      const int per = persist2d_elems_per_item(p.P);
+      const int64_t tot = p.nelem * p.batch;
+      for (int64_t e0 = 0; e0 < tot; e0 += per) {
+        WorkItem w{(int32_t)t, p.P, e0, (int32_t)std::min<int64_t>(per, tot - e0), 0};
+        its.push_back({w, (double)w.ne * p.P * p.P * p.P});
+      }
+    }
+    std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) { return a.cost > b.cost; });
+    std::vector<WorkItem> wl(its.size());
+    for (size_t i = 0; i < its.size(); ++i) wl[i] = its[i].w;
+    os.nitems = (int)wl.size();
+    int rc;
+    if ((rc = os.items.alloc(sizeof(WorkItem) * wl.size()))) return rc;
+    HIPCHK(hipMemcpy(os.items.p, wl.data(), sizeof(WorkItem) * wl.size(), hipMemcpyHostToDevice));
+    std::vector<Tables<double>> t64(MAXP + 1);
+    std::vector<Tables<float>> t32(MAXP + 1);
+    for (int P = 2; P <= MAXP; ++P) {
+      double xi[MAXP], w[MAXP], D[MAXP * MAXP];
+      gll_tables(P - 1, xi, w, D);
+      for (int i = 0; i < P * P; ++i) {
+        t64[P].D[i] = D[i];
+        t32[P].D[i] = (float)D[i];
+      }
+      for (int i = 0; i < P; ++i) {
+        t64[P].w[i] = w[i];
+        t32[P].w[i] = (float)w[i];
+      }
+    }
+    if ((rc = os.ptabs64.alloc(sizeof(Tables<double>) * t64.size()))) return rc;
+    if ((rc = os.ptabs32.alloc(sizeof(Tables<float>) * t32.size()))) return rc;
+    HIPCHK(hipMemcpy(os.ptabs64.p, t64.data(), sizeof(Tables<double>) * t64.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(os.ptabs32.p, t32.data(), sizeof(Tables<float>) * t32.size(), hipMemcpyHostToDevice));
+    os.persistent = 1;
+  }
   os.total_nodes = nodes0;
   if (os.fast) {
     int rc;
@@ -288,6 +346,14 @@ struct Integrator {
     if (cap) (void)hipStreamDestroy(cap);
   }
   void* b(int i) { return buf[i].p; }
+
+  // drop the captured graphs (after the operator's launch configuration changed)
+  void reset_graphs() {
+    if (gstep) (void)hipGraphExecDestroy(gstep);
+    if (gadj) (void)hipGraphExecDestroy(gadj);
+    gstep = gadj = nullptr;
+    ready = false;
+  }
 
   // one RK4 step on STATE (stage updates fused into the summation epilogues)
   hipError_t enqueue_step(hipStream_t s) {
@@ -333,10 +399,11 @@ struct Integrator {
   int prepare() {
     if (ready) return SEM_OK;
     for (int i = 0; i < NBUF; ++i) {
+      if (buf[i].p) continue;
       int rc = buf[i].alloc(n * ts);
       if (rc) return rc;
     }
-    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = enqueue_step(cap);
@@ -679,9 +746,94 @@ int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t
   return b->integ.adjoint(ckpt, nsteps, K, lam, work, b->stream);
 }
 
+int sem_batch_configure(sem_batch b, int32_t persistent, int32_t param) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  OpSet& os = b->os;
+  if (persistent) {
+    if (os.nitems == 0) return fail(SEM_ERR_UNSUPPORTED, "persistent launch needs a 2-D set of more than one problem");
+    if (param < 1 || param > 65535) return fail(SEM_ERR_ARG, "persistent grid %d outside 1..65535", param);
+    os.persistent = 1;
+    os.pgrid = param;
+  } else {
+    int choices[8];
+    for (auto& c : os.classes) {
+      const int n = elem_epb_choices(os.dim, c.P, choices, 8);
+      bool ok = param == 0;
+      for (int i = 0; i < n && !ok; ++i) ok = choices[i] == param;
+      c.epb = ok ? param : 0;  // orders without that choice keep their default
+    }
+    os.persistent = 0;
+  }
+  b->integ.reset_graphs();
+  return SEM_OK;
+}
+
+namespace {
+struct TuneResult {
+  int persistent, param;
+  double ms;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneResult> g_tune_cache;
+
+std::string batch_signature(const sem_batch_s* b) {
+  std::string k = std::to_string(b->descs[0].dim) + ":" + std::to_string(b->descs[0].dtype);
+  for (const auto& d : b->descs)
+    k += "|" + std::to_string(d.order) + "," + std::to_string(d.elems[0]) + "," + std::to_string(d.elems[1]) + "," +
+         std::to_string(d.elems[2]);
+  return k;
+}
+}  // namespace
+
 int sem_batch_autotune(sem_batch b, double* best_ms) {
   if (!b) return fail(SEM_ERR_ARG, "null batch");
-  if (best_ms) *best_ms = 0.0;
+  const std::string key = batch_signature(b);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      int rc = sem_batch_configure(b, it->second.persistent, it->second.param);
+      if (best_ms) *best_ms = it->second.ms;
+      return rc;
+    }
+  }
+  std::vector<std::pair<int, int>> cand = {{0, 0}, {0, 1}, {0, 2}, {0, 4}, {0, 8}, {0, 16}};
+  if (b->os.nitems > 0)
+    for (int g : {256, 512, 1024, 2048, 4096}) cand.push_back({1, g});
+  hipStream_t s = b->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  TuneResult best{0, 0, 1e30};
+  int rc = SEM_OK;
+  for (auto [pm, prm] : cand) {
+    if ((rc = sem_batch_configure(b, pm, prm))) break;
+    if ((rc = b->integ.prepare())) break;
+    // time the captured RK4 step on a zero state (values do not change the work)
+    hipError_t he = hipMemsetAsync(b->integ.b(Integrator::STATE), 0, b->integ.n * b->integ.ts, s);
+    for (int w = 0; w < 2 && he == hipSuccess; ++w) he = hipGraphLaunch(b->integ.gstep, s);
+    if (he == hipSuccess) he = hipEventRecord(e0, s);
+    const int R = 5;
+    for (int r = 0; r < R && he == hipSuccess; ++r) he = hipGraphLaunch(b->integ.gstep, s);
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) {
+      rc = fail(SEM_ERR_HIP, "autotune timing: %s", hipGetErrorString(he));
+      break;
+    }
+    if (ms / R < best.ms) best = {pm, prm, ms / R};
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if ((rc = sem_batch_configure(b, best.persistent, best.param))) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  if (best_ms) *best_ms = best.ms;
   return SEM_OK;
 }
 

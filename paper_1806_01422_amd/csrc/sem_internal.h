@@ -74,6 +74,21 @@ hipError_t launch_dss(const ProbDev* probs, int32_t nprobs, int64_t nitems, int 
 // elements-per-workgroup choices accepted by launch_elem for (dim, P); returns count, fills out[]
 int elem_epb_choices(int dim, int P, int* out, int max_out);
 
+// Work item of the persistent 2-D element kernel: elements [e0, e0 + ne) (batch-flattened) of
+// problem `prob` (index into the problem table), whose order has P points per direction.
+struct WorkItem {
+  int32_t prob;
+  int32_t P;
+  int64_t e0;
+  int32_t ne;
+  int32_t pad;
+};
+// One launch over all items of a mixed-order 2-D set; tabs: device array of Tables<T> indexed by
+// P (entries 0..MAXP).  Each workgroup of 256 threads walks items blockIdx.x + k * grid.
+hipError_t launch_persist2d(const ProbDev* probs, const WorkItem* items, int nitems, int grid, int op, int dtype,
+                            const void* tabs, const void* u, const void* v, void* lvec, Coef in_scale, hipStream_t s);
+int persist2d_elems_per_item(int P);  // elements per work item for order P
+
 // Host GLL tables in long double (gll.cpp)
 void gll_tables(int N, double* xi, double* w, double* D);
 

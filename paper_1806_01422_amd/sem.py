@@ -51,6 +51,7 @@ _SIGS = {
     "sem_batch_rk4_forward": [_vp, _vp, _i32, _i32, _vp],
     "sem_batch_rk4_adjoint": [_vp, _vp, _i32, _i32, _vp, _vp],
     "sem_batch_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
+    "sem_batch_configure": [_vp, _i32, _i32],
     "sem_batch_autotune": [_vp, ctypes.POINTER(_f64)],
 }
 EXPORTED = tuple(_SIGS)
@@ -326,7 +327,13 @@ class Batch:
         _call(lib().sem_batch_rk4_adjoint(self._h, _ptr(ckpt), int(nsteps), int(ckpt_every), _ptr(lam), _ptr(work)))
         return lam
 
+    def configure(self, persistent, param=0):
+        """persistent=True: one persistent launch with `param` workgroups; False: one launch per
+        order class with `param` elements per workgroup (0 = default)."""
+        _call(lib().sem_batch_configure(self._h, 1 if persistent else 0, int(param)))
+
     def autotune(self):
+        """Time the candidate launch shapes on one RK4 step and keep the fastest; returns its ms."""
         ms = _f64()
         _call(lib().sem_batch_autotune(self._h, ctypes.byref(ms)))
         return ms.value

@@ -313,3 +313,29 @@ def test_nonfinite_detection(P):
     c.rk4_forward(u, 1e-3, 10)
     with pytest.raises(P.SemError):
         c.rk4_forward(u, 5.0, 200)  # far beyond the stability limit
+
+
+def test_batch_launch_shapes_and_autotune(P):
+    note("batched uneven set (C5 recipe, 20 problems): launch shapes bitwise equal, autotune")
+    specs, probs = batch_problems(20)
+    B = P.Batch(specs)
+    u = B.empty()
+    w = B.empty()
+    for i, (s, p) in enumerate(zip(specs, probs)):
+        m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
+        xs = [m.coords(k) for k in range(2)]
+        B.view(u, i).copy_(gpu(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]))
+        B.view(w, i).copy_(gpu(wl.normal_field(m.shape, p.target_seed)))
+    B.configure(True, 1024)
+    f0, j0 = B.rhs(u), B.jact_vec(u, w)
+    u1, _ = B.rk4_forward(u, 6, 0)
+    for persistent, param in [(True, 7), (True, 300), (False, 0), (False, 1), (False, 4), (False, 16)]:
+        B.configure(persistent, param)
+        assert torch.equal(B.rhs(u), f0), (persistent, param)
+        assert torch.equal(B.jact_vec(u, w), j0), (persistent, param)
+        assert torch.equal(B.rk4_forward(u, 6, 0)[0], u1), (persistent, param)
+    ms = B.autotune()
+    assert ms > 0
+    assert torch.equal(B.rhs(u), f0) and torch.equal(B.rk4_forward(u, 6, 0)[0], u1)
+    with pytest.raises(P.SemError):
+        B.configure(True, 0)
