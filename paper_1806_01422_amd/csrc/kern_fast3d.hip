@@ -255,14 +255,15 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
     return -1;
   };
 
-  auto load_z = [&](int ex, T (&UU)[3][8], T (&VV)[3][8]) {
+  auto load_z = [&](int ex, T (&UU)[3][8], T (&VV)[3][8], bool lu, bool lv) {
     const int gx = (7 * ex + l0) % g.nx;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        UU[i][c] = ub[i * g.nodes + zoff[c] + gx];
-        if constexpr (HASV) VV[i][c] = vb[i * g.nodes + zoff[c] + gx];
+        if (lu) UU[i][c] = ub[i * g.nodes + zoff[c] + gx];
+        if constexpr (HASV)
+          if (lv) VV[i][c] = vb[i * g.nodes + zoff[c] + gx];
       }
   };
 
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
           if (EP >= 2) bstore(r_o2, (own && !surf) ? no : OOB, a2 * E2[i][c] + b2 * sm);
         }
         const int fp = fplane_of(c);
-        if (wy == 1 || wz == 1) {  // waves without face-buffer planes skip these stores entirely
+        if (wy == 1 || (wz == 1 && c == 7)) {  // only slots that can hold face-buffer planes store
           bstore(r_fb, (ina && fp >= 0) ? (uint32_t)(((i * FROWS + fp) * g.nx + 7 * ex + l0) * sizeof(T)) : OOB, r);
         }
       }
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   T* __restrict__ tQ = sQ[wave][0];
   T* __restrict__ tV = HASV ? sV[wave][0] : sU[wave][0];
   T cu[3][8], cv[3][8];
-  load_z(0, cu, cv);
+  load_z(0, cu, cv, true, true);
   T carry[3] = {0, 0, 0}, first0[3] = {0, 0, 0};
 
   for (int ex = 0; ex < g.Ex; ++ex) {
@@ -396,7 +397,8 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
         });
     // the z-map lines are no longer needed: prefetch the next element into the same registers
     // (unconditionally: the last step reloads element 0, so the memory-op sequence is fixed)
-    load_z(ex + 1 < g.Ex ? ex + 1 : 0, cu, cv);
+    const int exn = ex + 1 < g.Ex ? ex + 1 : 0;
+    load_z(exn, cu, cv, true, true);
     wave_sync();
     // ---- y-map (lane (a=l0, c=l1), register b)
     map_contrib<T, OP>(
