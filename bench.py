@@ -6,7 +6,7 @@ elements of order N = 7 (33,718,272 unique DOF, FP64), one step applies F(u) and
 the J^T/F cost ratio, the FP32 variant, adjoint gradients/s of the 64-IC 2-D configuration and the
 batched-vs-plain gradient/s of the 128 uneven 2-D problems are reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu] [--calib-copy]
 """
 import argparse
 import json
@@ -23,6 +23,24 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E datasheet peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fast3d_jact_32cube_n7.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_1806_01422_amd", "csrc", "kern_fast3d.hip")
+
+
+def measured_traffic():
+    """HBM bytes per J^T apply from the committed FETCH_SIZE/WRITE_SIZE counter summary, or None
+    when that summary is absent or was taken on a different version of the kernel source."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("source_sha256:",
+                                                                                      "traffic_bytes_per_launch:")))
+    if fields.get("source_sha256", "").strip() != src or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -149,6 +167,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain elementwise copy of one field (known bytes) for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path runs on one MI355X, "
@@ -200,11 +220,18 @@ def main():
         "f_gdofs": round(dof / t_f / 1e6, 3), "jt_gdofs": round(dof / t_jt / 1e6, 3),
         "jv_gdofs": round(dof / t_jv / 1e6, 3), "jt_over_f": round(t_jt / t_f, 4),
         "f_ms": round(t_f, 5), "jt_ms": round(t_jt, 5), "jv_ms": round(t_jv, 5),
-        "roofline": {"bound": "hbm", "kernel": "J^T w apply", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "J^T w apply: fast3d_kernel (J^T) + fast3d_fixup", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic()},
         "f_hbm_frac": round(16.0 * dof / (t_f / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
     }
+    if args.calib_copy:
+        # A plain copy of one field (read 8 B, write 8 B per DOF): the reference dispatch against
+        # which the FETCH_SIZE / WRITE_SIZE counters are scaled.
+        for _ in range(5):
+            torch.neg(U, out=JV)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 5 x {8 * dof} bytes read and written")
     ctx.close()
     del U, V, W, F, JT, JV
     torch.cuda.empty_cache()
