@@ -1,32 +1,47 @@
 // Tuned 3-D kernels for order N = 7 (8 GLL points per direction) on gfx950.
 //
-// Work decomposition.  A workgroup of 4 wavefronts owns a 2 x 2 block of element rows in (y, z);
-// each wavefront owns one row and sweeps it along x, one element per step, its 64 lanes covering
-// the 8 x 8 lines of the element.  Every lane keeps whole element lines in registers in one of
-// three maps:
-//     z-map  lane = a + 8b, register c      (global loads: 8 lanes read 64 contiguous bytes)
+// Work decomposition.  A workgroup of 4 wavefronts owns 4 consecutive elements along x of one
+// element row in y (wavefront w takes element 4X + w) and sweeps that block along z, one element
+// layer per step.  Concurrently running wavefronts therefore touch contiguous x-ranges: the 4
+// wavefronts of a workgroup read and write 224 contiguous bytes of every grid row they cover, and
+// the workgroups of one XCD (block ids are remapped so that each XCD holds a contiguous band of
+// element rows) cover whole rows.  Lines shared by neighbouring elements are then fetched once and
+// written whole, instead of once per element step as in a sweep along x.
+//
+// Every lane keeps whole element lines in registers in one of three maps:
+//     z-map  lane = a + 8b, register c      (global loads and stores: 8 lanes, 64 contiguous bytes)
 //     y-map  lane = a + 8c, register b
-//     x-map  lane = b + 8c, register a      (output, x-direction summation)
+//     x-map  lane = b + 8c, register a      (x-direction summation)
 // with (a, b, c) the element-local (x, y, z) GLL indices.  The element tile moves between maps
 // through an XOR-swizzled LDS tile.  The contraction with D along the register direction uses
 // the centro-antisymmetry of the GLL differentiation matrix (D_{N-i,N-j} = -D_ij): even/odd
 // halves of the line need 32 multiply-adds instead of 64 (Sec. 3.3 sum factorisation, one
 // direction at a time).
 //
-// Direct-stiffness summation.  Along x the last point (a = 7) of an element is the first point
-// (a = 0) of the next: it is carried in registers to the next step, and the periodic wrap is
-// closed after the sweep.  Between the four rows of a workgroup the y- and z-faces are added
-// through LDS.  Nodes on the workgroup's own lower y/z boundary planes receive contributions from
-// neighbouring workgroups: the kernel writes its partial sum there, neighbours write theirs to a
-// face buffer, and fast3d_fixup adds them, divides by the mass and applies the epilogue.
+// Direct-stiffness summation (Q^T).
+//   z: the last plane (c = 7) of an element is the first plane (c = 0) of the next one in the
+//      sweep; its partial sum is carried in registers, and the periodic wrap is closed after the
+//      sweep.  The input plane is carried too, so each step loads 7 new planes.
+//   x: inside a workgroup the shared face of wavefronts w and w + 1 is added through LDS.
+//   workgroup faces: a workgroup owns the nodes x in [28X, 28X + 28), y in [7ey, 7ey + 7).  It
+//      writes its partial sum of the lower y-row (y = 7ey) to the output, and to a face buffer its
+//      contributions to the upper y-row and upper x-column (owned by the neighbours) and the
+//      first 32-byte sector of each of its interior rows (x in [28X, 28X + 4): the x = 28X node
+//      still lacks the left neighbour's part).  fast3d_fixup adds the parts, applies the inverse
+//      mass and the epilogue, and writes those nodes as whole row segments and whole sectors.
 #include "sem_internal.h"
 
 namespace sem {
 namespace {
 
-constexpr int NQ = 7;       // order
-constexpr int FROWS = 29;   // face-buffer planes per workgroup: 15 (y-local 14) + 14 (z-local 14)
-constexpr int SROWS = 27;   // owned boundary rows per workgroup: 14 (y-local 0) + 13 (z-local 0)
+constexpr int NQ = 7;  // order
+constexpr int WX = 4;  // elements per workgroup along x, one per wavefront
+// Face buffer: per (workgroup, component, grid plane z) FROWS values,
+constexpr int FB_UY = 0;   //   upper y-row y = 7ey + 7, x-local 0..28 (29 values)
+constexpr int FB_UX = 29;  //   upper x-column x = 28X + 28, y-local 0..6 (7 values)
+constexpr int FB_LX = 36;  //   first sector x-local 0..3 of the rows y-local 1..6 (24 values)
+constexpr int FROWS = 60;
+constexpr int FIXN = 52;   // nodes the fixup completes per (workgroup, component, z): 28 + 24
 
 // The even/odd blocks of D are A[i][m] = (D_im - D_i,7-m)/2 and B[i][m] = (D_im + D_i,7-m)/2
 // (i, m < 4).  Centro-antisymmetry makes the blocks of D^T their transposes (A' = B^T, B' = A^T),
@@ -40,7 +55,7 @@ struct FastTab {
 
 struct FastArgs {
   int Ex, Ey, Ez, nx, ny, nz;
-  int NWy, NWz;  // workgroup grid
+  int NX, NWG;  // workgroups along x (Ex / 4) and per field (NX * Ey)
   double hh[3], sc[3], nu;
   int64_t nodes;  // per component
   const ProbDev* prob;
@@ -191,6 +206,13 @@ __device__ __forceinline__ T coef(const Coef& c, double dt) {
   return (T)(c.c0 + c.cdt * dt);
 }
 
+// Workgroup (X, ey) of block `bid`.  Blocks are dealt round-robin to the 8 XCDs; when the count
+// allows, consecutive logical workgroups are given to the same XCD so that it sweeps a contiguous
+// band of element rows and its L2 serves the rows shared by neighbouring workgroups.
+__device__ __forceinline__ int logical_wg(int bid, int nwg) {
+  return (nwg % 8 == 0) ? (bid % 8) * (nwg / 8) + bid / 8 : bid;
+}
+
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
 // 2 = additionally o2 = a2 x2 + b2 s.
 template <typename T, int OP, int EP>
@@ -201,14 +223,12 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   __shared__ T sU[4][3][512];
   __shared__ T sV[4][HASV ? 3 : 1][HASV ? 512 : 1];
   __shared__ T sQ[4][3][512];
-  __shared__ T sEy[2][3][64];
-  __shared__ T sEz[2][3][64];
+  __shared__ T sEx[2][3][3][64];  // [step parity][sending wavefront][component][x-map lane]
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wy = wave & 1, wz = wave >> 1;
-  const int wg = blockIdx.x;
-  const int Y = wg % g.NWy, Z = wg / g.NWy;
-  const int ey = 2 * Y + wy, ez = 2 * Z + wz;
+  const int L = logical_wg(blockIdx.x, g.NWG);
+  const int X = L % g.NX, ey = L / g.NX;
+  const int ex = WX * X + wave;
   const int64_t bo = (int64_t)blockIdx.y * 3 * g.nodes;  // batch member offset
   const T* __restrict__ ub = u + bo;
   const T* __restrict__ vb = HASV ? v + bo : nullptr;
@@ -217,9 +237,8 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   const __amdgpu_buffer_rsrc_t r_x1 = brsrc(EP >= 1 ? static_cast<const T*>(epi.x1) + bo : u, EP >= 1 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_o2 = brsrc(EP >= 2 ? static_cast<T*>(epi.o2) + bo : u, EP >= 2 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_x2 = brsrc(EP >= 2 ? static_cast<const T*>(epi.x2) + bo : u, EP >= 2 ? fbytes : 0);
-  const __amdgpu_buffer_rsrc_t r_fb =
-      brsrc(face + ((int64_t)blockIdx.y * g.NWy * g.NWz + wg) * 3 * FROWS * g.nx,
-            (uint32_t)(3 * FROWS * g.nx * sizeof(T)));
+  const __amdgpu_buffer_rsrc_t r_fb = brsrc(face + ((int64_t)blockIdx.y * g.NWG + L) * 3 * g.nz * FROWS,
+                                            (uint32_t)(3 * g.nz * FROWS * sizeof(T)));
   const double dt = g.prob->dt;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
 
@@ -232,90 +251,86 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   for (int s = 0; s < 8; ++s) om[s] = (T)(g.hh[0] * g.hh[1] * g.hh[2]) * tb->w[l0] * tb->w[l1] * tb->w[s];
   const T K1x = (T)(g.nu * g.sc[0] * g.sc[0]), K1y = (T)(g.nu * g.sc[1] * g.sc[1]), K1z = (T)(g.nu * g.sc[2] * g.sc[2]);
   const T K2x = (T)g.sc[0], K2y = (T)g.sc[1], K2z = (T)g.sc[2];
-  // inverse assembled mass, lane factor: (b=l0, c=l1) in the x-map, (a=l0, b=l1) in the z-map
+  // inverse assembled mass, lane factor of the z-map (a = l0, b = l1)
   const T mlane = tb->imq[l0] * tb->imq[l1] * ihhh;
   const T zin = (T)(in_scale.c0 + in_scale.cdt * dt) * mlane;  // J^T input: scale * M^{-1} w
 
-  // z-map global addressing: lane (a=l0, b=l1), register c
-  const int64_t rowy = (int64_t)((7 * ey + l1) % g.ny) * g.nx;
-  int64_t zoff[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) zoff[c] = (int64_t)((7 * ez + c) % g.nz) * g.ny * g.nx + rowy;
-  // Output in the z-map: lane (a=l0, b=l1), register c, node (7ex + a, 7ey + b, 7ez + c).  The node
-  // is owned by this row when a, b, c < 7; it lies on the workgroup's lower y/z boundary planes
-  // (partial sum, completed later) when (wy == 0 && b == 0) or (wz == 0 && c == 0); the upper
-  // planes (wy == 1 && b == 7, wz == 1 && c == 7) go to the face buffer.
-  const bool xown = l0 < 7;
-  const int64_t orowz = ((int64_t)(7 * ey + l1) % g.ny) * g.nx;  // y row of the lane (b < 7: no wrap)
-  auto zrow = [&](int c) { return (int64_t)(7 * ez + c) * g.ny * g.nx; };  // c < 7 only
-  // face-buffer plane of (b = l1, c), -1 if none
-  auto fplane_of = [&](int c) -> int {
-    if (wy == 1 && l1 == 7 && !(wz == 0 && c == 7)) return 7 * wz + c;  // y-local 14, z-local 7wz+c
-    if (wz == 1 && c == 7 && l1 < 7) return 15 + 7 * wy + l1;           // z-local 14, y-local 7wy+b
-    return -1;
-  };
+  // z-map global addressing: lane (a = l0, b = l1), register c
+  const int64_t plane = (int64_t)g.ny * g.nx;
+  const int64_t lrow = (int64_t)((7 * ey + l1) % g.ny) * g.nx + (7 * ex + l0) % g.nx;
+  // Output roles of the lane's node (7ex + a, 7ey + b, z):
+  //   own   a < 7, b < 7, outside the first sector of an interior row: written here (b = 0: the
+  //         partial sum of the lower y-row, completed by the fixup; b > 0: final value)
+  //   fbk   face-buffer slot (upper y-row, upper x-column, first sectors), -1 if none
+  const int a = l0, b = l1;
+  const bool lsec = wave == 0 && a < 4 && b >= 1 && b < 7;
+  const bool own = a < 7 && b < 7 && !lsec;
+  const bool partial = b == 0;
+  int fbk = -1;
+  if (b == 7) fbk = a < 7 ? FB_UY + 7 * wave + a : (wave == WX - 1 ? FB_UY + 28 : -1);
+  else if (wave == WX - 1 && a == 7) fbk = FB_UX + b;
+  else if (lsec) fbk = FB_LX + 4 * (b - 1) + a;
+  const int64_t orow = (int64_t)(7 * ey + b) * g.nx + 7 * ex + a;  // valid when own
 
-  auto load_z = [&](int ex, T (&UU)[3][8], T (&VV)[3][8], bool lu, bool lv) {
-    const int gx = (7 * ex + l0) % g.nx;
+  // Load planes c in [c0, 8) of element layer ez (plane 7ez + c, periodic in z).
+  auto load_z = [&](int ez, int c0, T (&UU)[3][8], T (&VV)[3][8]) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < 8; ++c) {
+      if (c < c0) continue;
+      int zc = 7 * ez + c;
+      if (zc >= g.nz) zc -= g.nz;
+      const int64_t off = zc * plane + lrow;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (lu) UU[i][c] = ub[i * g.nodes + zoff[c] + gx];
-        if constexpr (HASV)
-          if (lv) VV[i][c] = vb[i * g.nodes + zoff[c] + gx];
+      for (int i = 0; i < 3; ++i) {
+        UU[i][c] = ub[i * g.nodes + off];
+        if constexpr (HASV) VV[i][c] = vb[i * g.nodes + off];
       }
+    }
   };
 
-  // Write element ex from the z-map values Z[i][c] (read back from LDS after the x-map summation):
-  // finished nodes get M^{-1} and the epilogue, nodes on the workgroup's lower boundary planes the
-  // partial sum, the upper planes go to the face buffer.  a_lo excludes the x-plane a = 0 of element
-  // 0 until the periodic wrap is added.  Every lane issues the same stores; inactive ones drop.
-  auto emit = [&](int ex, const T (&Zv)[3][8], int a_lo, int a_hi, const T (&E1)[3][7], const T (&E2)[3][7]) {
-    const bool ina = xown && l0 >= a_lo && l0 < a_hi;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const T r = Zv[i][c];
-        if (c < 7) {
-          const bool own = ina && l1 < 7;
-          const bool surf = (wy == 0 && l1 == 0) || (wz == 0 && c == 0);
-          const uint32_t no = (uint32_t)((i * g.nodes + zrow(c) + orowz + 7 * ex + l0) * sizeof(T));
-          const T sm = (OP != OP_JACT) ? r * (mlane * tb->imq[c]) : r;
-          T r1 = b1 * sm;
-          if (EP >= 1) r1 += a1 * E1[i][c];
-          bstore(r_o1, own ? no : OOB, surf ? r : r1);
-          if (EP >= 2) bstore(r_o2, (own && !surf) ? no : OOB, a2 * E2[i][c] + b2 * sm);
-        }
-        const int fp = fplane_of(c);
-        if (wy == 1 || (wz == 1 && c == 7)) {  // only slots that can hold face-buffer planes store
-          bstore(r_fb, (ina && fp >= 0) ? (uint32_t)(((i * FROWS + fp) * g.nx + 7 * ex + l0) * sizeof(T)) : OOB, r);
-        }
-      }
-  };
-
-  auto load_epi = [&](int ex, T (&E1)[3][7], T (&E2)[3][7], int a_lo, int a_hi) {
-    const bool ina = xown && l0 >= a_lo && l0 < a_hi && l1 < 7;
+  // Write planes c in [c_lo, c_hi) of element layer ez from the summed z-map values Zv: inverse
+  // mass and epilogue for finished nodes, the raw partial sum on the lower y-row, and the
+  // face-buffer slots.  Every lane issues the same stores; inactive ones drop theirs.
+  auto emit = [&](int ez, const T (&Zv)[3][8], int c_lo, int c_hi, const T (&E1)[3][7], const T (&E2)[3][7]) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int c = 0; c < 7; ++c) {
-        const bool surf = (wy == 0 && l1 == 0) || (wz == 0 && c == 0);
-        const uint32_t no =
-            (ina && !surf) ? (uint32_t)((i * g.nodes + zrow(c) + orowz + 7 * ex + l0) * sizeof(T)) : OOB;
+        const bool inc = c >= c_lo && c < c_hi;
+        const int z = 7 * ez + c;  // < nz: c < 7
+        const T r = Zv[i][c];
+        const uint32_t no = (uint32_t)((i * g.nodes + z * plane + orow) * sizeof(T));
+        const T sm = (OP != OP_JACT) ? r * (mlane * tb->imq[c]) : r;
+        T r1 = b1 * sm;
+        if (EP >= 1) r1 += a1 * E1[i][c];
+        bstore(r_o1, (own && inc) ? no : OOB, partial ? r : r1);
+        if (EP >= 2) bstore(r_o2, (own && inc && !partial) ? no : OOB, a2 * E2[i][c] + b2 * sm);
+        const uint32_t fo = (uint32_t)((((int64_t)i * g.nz + z) * FROWS + fbk) * sizeof(T));
+        bstore(r_fb, (fbk >= 0 && inc) ? fo : OOB, r);
+      }
+  };
+
+  auto load_epi = [&](int ez, T (&E1)[3][7], T (&E2)[3][7], int c_lo, int c_hi) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) {
+        const bool inc = c >= c_lo && c < c_hi;
+        const uint32_t no = (own && !partial && inc)
+                                ? (uint32_t)((i * g.nodes + (7 * ez + c) * plane + orow) * sizeof(T))
+                                : OOB;
         E1[i][c] = (EP >= 1) ? bload<T>(r_x1, no) : (T)0;
         E2[i][c] = (EP >= 2) ? bload<T>(r_x2, no) : (T)0;
       }
   };
 
-  // x-map registers -> LDS tile -> z-map registers (after the summations along x, y, z)
+  // x-map registers -> LDS tile -> z-map registers
   auto to_zmap = [&](const T (&R)[3][8], T (&Zv)[3][8], T* __restrict__ tile) {
     wave_sync();
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int a = 0; a < 8; ++a) tile[i * 512 + tix(a, l0, l1)] = R[i][a];
+      for (int q = 0; q < 8; ++q) tile[i * 512 + tix(q, l0, l1)] = R[i][q];
     wave_sync();
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -324,49 +339,18 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
     wave_sync();
   };
 
-  // y then z exchange of the shared faces inside the workgroup (x-map registers [0, na))
-  auto exchange = [&](T (&R)[3][8], int na) {
-    if (wy == 0 && l0 == 7) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int a = 0; a < 7; ++a)
-          if (a < na) sEy[wz][i][l1 * 8 + a] = R[i][a];
-    }
-    __syncthreads();
-    if (wy == 1 && l0 == 0) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int a = 0; a < 7; ++a)
-          if (a < na) R[i][a] += sEy[wz][i][l1 * 8 + a];
-    }
-    if (wz == 0 && l1 == 7) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int a = 0; a < 7; ++a)
-          if (a < na) sEz[wy][i][l0 * 8 + a] = R[i][a];
-    }
-    __syncthreads();
-    if (wz == 1 && l1 == 0) {
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int a = 0; a < 7; ++a)
-          if (a < na) R[i][a] += sEz[wy][i][l0 * 8 + a];
-    }
-  };
-
   T* __restrict__ tU = sU[wave][0];
   T* __restrict__ tQ = sQ[wave][0];
   T* __restrict__ tV = HASV ? sV[wave][0] : sU[wave][0];
   T cu[3][8], cv[3][8];
-  load_z(0, cu, cv, true, true);
+  load_z(0, 0, cu, cv);
   T carry[3] = {0, 0, 0}, first0[3] = {0, 0, 0};
 
-  for (int ex = 0; ex < g.Ex; ++ex) {
+  for (int ez = 0; ez < g.Ez; ++ez) {
     // ---- z-map (lane (a=l0, b=l1), register c): stage the element tile, z-direction part
+    T wlast[3];  // unscaled input plane c = 7, the next layer's plane c = 0
+#pragma unroll
+    for (int i = 0; i < 3; ++i) wlast[i] = cv[i][7];
     if constexpr (OP == OP_JACT) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
@@ -382,136 +366,150 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
       }
     map_contrib<T, OP>(
         2,
-        [&](int i, T (&X)[8]) {
+        [&](int i, T (&Xr)[8]) {
 #pragma unroll
-          for (int c = 0; c < 8; ++c) X[c] = cu[i][c];
+          for (int c = 0; c < 8; ++c) Xr[c] = cu[i][c];
         },
-        [&](int i, T (&X)[8]) {
+        [&](int i, T (&Xr)[8]) {
 #pragma unroll
-          for (int c = 0; c < 8; ++c) X[c] = cv[i][c];
+          for (int c = 0; c < 8; ++c) Xr[c] = cv[i][c];
         },
         om, K1z, K2z, tb,
         [&](int i, const T (&P)[8]) {
 #pragma unroll
           for (int c = 0; c < 8; ++c) tQ[i * 512 + tix(l0, l1, c)] = P[c];
         });
-    // the z-map lines are no longer needed: prefetch the next element into the same registers
-    // (unconditionally: the last step reloads element 0, so the memory-op sequence is fixed)
-    const int exn = ex + 1 < g.Ex ? ex + 1 : 0;
-    load_z(exn, cu, cv, true, true);
+    // the z-map lines are no longer needed: move plane 7 to plane 0 and prefetch the next layer's
+    // planes 1..7 into the same registers (unconditionally: the last step reloads layer 0, so the
+    // memory-op sequence is fixed)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      cu[i][0] = cu[i][7];
+      if constexpr (HASV) cv[i][0] = wlast[i];
+    }
+    load_z(ez + 1 < g.Ez ? ez + 1 : 0, 1, cu, cv);
     wave_sync();
     // ---- y-map (lane (a=l0, c=l1), register b)
     map_contrib<T, OP>(
         1,
-        [&](int i, T (&X)[8]) {
+        [&](int i, T (&Xr)[8]) {
 #pragma unroll
-          for (int b = 0; b < 8; ++b) X[b] = tU[i * 512 + tix(l0, b, l1)];
+          for (int q = 0; q < 8; ++q) Xr[q] = tU[i * 512 + tix(l0, q, l1)];
         },
-        [&](int i, T (&X)[8]) {
+        [&](int i, T (&Xr)[8]) {
 #pragma unroll
-          for (int b = 0; b < 8; ++b) X[b] = tV[i * 512 + tix(l0, b, l1)];
+          for (int q = 0; q < 8; ++q) Xr[q] = tV[i * 512 + tix(l0, q, l1)];
         },
         om, K1y, K2y, tb,
         [&](int i, const T (&P)[8]) {
           // read the 8 values first, then write: one LDS round trip per component instead of
           // one per value (the compiler cannot prove the swizzled addresses distinct)
-          T q[8];
+          T qv[8];
 #pragma unroll
-          for (int b = 0; b < 8; ++b) q[b] = tQ[i * 512 + tix(l0, b, l1)];
+          for (int q = 0; q < 8; ++q) qv[q] = tQ[i * 512 + tix(l0, q, l1)];
 #pragma unroll
-          for (int b = 0; b < 8; ++b) tQ[i * 512 + tix(l0, b, l1)] = q[b] + P[b];
+          for (int q = 0; q < 8; ++q) tQ[i * 512 + tix(l0, q, l1)] = qv[q] + P[q];
         });
     wave_sync();
     // ---- x-map (lane (b=l0, c=l1), register a)
     T R[3][8];
     map_contrib<T, OP>(
         0,
-        [&](int i, T (&X)[8]) {
+        [&](int i, T (&Xr)[8]) {
 #pragma unroll
-          for (int a = 0; a < 8; ++a) X[a] = tU[i * 512 + tix(a, l0, l1)];
+          for (int q = 0; q < 8; ++q) Xr[q] = tU[i * 512 + tix(q, l0, l1)];
         },
-        [&](int i, T (&X)[8]) {
+        [&](int i, T (&Xr)[8]) {
 #pragma unroll
-          for (int a = 0; a < 8; ++a) X[a] = tV[i * 512 + tix(a, l0, l1)];
+          for (int q = 0; q < 8; ++q) Xr[q] = tV[i * 512 + tix(q, l0, l1)];
         },
         om, K1x, K2x, tb,
         [&](int i, const T (&P)[8]) {
 #pragma unroll
-          for (int a = 0; a < 8; ++a) R[i][a] = P[a] + tQ[i * 512 + tix(a, l0, l1)];
+          for (int q = 0; q < 8; ++q) R[i][q] = P[q] + tQ[i * 512 + tix(q, l0, l1)];
         });
-    // ---- x-direction summation: carry the shared face to the next element
+    // ---- x-direction summation inside the workgroup: wavefront w's face a = 7 is wavefront
+    // w + 1's face a = 0 (double-buffered by step parity: one barrier per step)
+    const int par = ez & 1;
+    if (wave < WX - 1) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) sEx[par][wave][i][lane] = R[i][7];
+    }
+    __syncthreads();
+    if (wave > 0) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) R[i][0] += sEx[par][wave - 1][i][lane];
+    }
+    // ---- to the z-map; z-direction summation: carry the shared plane to the next layer
+    T Zv[3][8];
+    to_zmap(R, Zv, tQ);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      R[i][0] += carry[i];
-      carry[i] = R[i][7];
+      Zv[i][0] += carry[i];
+      carry[i] = Zv[i][7];
     }
-    exchange(R, 7);
-    if (ex == 0) {
+    if (ez == 0) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) first0[i] = R[i][0];
+      for (int i = 0; i < 3; ++i) first0[i] = Zv[i][0];
     }
-    // ---- outputs, written from the z-map so that 8 lanes store one contiguous row segment
+    // ---- outputs (plane c = 0 of layer 0 waits for the periodic wrap)
     {
-      T Zv[3][8], E1[3][7], E2[3][7];
-      load_epi(ex, E1, E2, ex == 0 ? 1 : 0, 7);
-      to_zmap(R, Zv, tQ);
-      emit(ex, Zv, ex == 0 ? 1 : 0, 7, E1, E2);
+      T E1[3][7], E2[3][7];
+      load_epi(ez, E1, E2, ez == 0 ? 1 : 0, 7);
+      emit(ez, Zv, ez == 0 ? 1 : 0, 7, E1, E2);
     }
   }
-  // periodic wrap along x: the carried face of the last element belongs to the first element
+  // periodic wrap along z: the carried plane of the last layer is plane c = 0 of layer 0
   {
-    T R[3][8];
+    T Zv[3][8], E1[3][7], E2[3][7];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int a = 0; a < 8; ++a) R[i][a] = (a == 0) ? carry[i] : (T)0;
-    exchange(R, 1);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) R[i][0] += first0[i];
-    T Zv[3][8], E1[3][7], E2[3][7];
+      for (int c = 0; c < 8; ++c) Zv[i][c] = (c == 0) ? first0[i] + carry[i] : (T)0;
     load_epi(0, E1, E2, 0, 1);
-    to_zmap(R, Zv, tQ);
     emit(0, Zv, 0, 1, E1, E2);
   }
 }
 
-// Completes the nodes on each workgroup's lower y/z boundary planes: own partial (in o1) plus the
-// neighbours' face-buffer partials, inverse mass (F, J v) and epilogue.
+// Completes, for every workgroup (X, ey), component and grid plane z, the nodes of its lower
+// y-row (own partial in o1 plus the lower neighbour's upper-y contribution) and of the first
+// sectors of its interior rows (face-buffer value plus, at x = 28X, the left neighbour's upper-x
+// contribution); the node (28X, 7ey) also receives the diagonal neighbour's corner.  Then the
+// inverse mass (F, J v) and the epilogue.
 template <typename T, bool DIV>
 __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                     const T* __restrict__ face, Epi epi, int batch) {
-  const int NWG = g.NWy * g.NWz;
-  const int64_t total = (int64_t)batch * NWG * 3 * SROWS * g.nx;
+  const int64_t total = (int64_t)batch * g.NWG * 3 * g.nz * FIXN;
   int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= total) return;
-  const int x = (int)(t % g.nx);
-  t /= g.nx;
-  const int srow = (int)(t % SROWS);
-  t /= SROWS;
+  const int k = (int)(t % FIXN);
+  t /= FIXN;
+  const int z = (int)(t % g.nz);
+  t /= g.nz;
   const int i = (int)(t % 3);
   t /= 3;
-  const int wg = (int)(t % NWG);
-  const int b = (int)(t / NWG);
-  const int Y = wg % g.NWy, Z = wg / g.NWy;
-  const int yl = srow < 14 ? 0 : srow - 13;
-  const int zl = srow < 14 ? srow : 0;
-  const int gy = 14 * Y + yl, gz = 14 * Z + zl;
-  const int64_t bo = (int64_t)b * 3 * g.nodes;
-  const int64_t o = bo + i * g.nodes + ((int64_t)gz * g.ny + gy) * g.nx + x;
+  const int L = (int)(t % g.NWG);
+  const int bm = (int)(t / g.NWG);
+  const int X = L % g.NX, ey = L / g.NX;
+  const int Xm = (X - 1 + g.NX) % g.NX, eym = (ey - 1 + g.Ey) % g.Ey;
+  const int xl = k < 28 ? k : (k - 28) % 4;
+  const int yl = k < 28 ? 0 : 1 + (k - 28) / 4;
+  const int64_t bo = (int64_t)bm * 3 * g.nodes;
+  const int64_t o = bo + i * g.nodes + ((int64_t)z * g.ny + 7 * ey + yl) * g.nx + 7 * WX * X + xl;
   T* __restrict__ o1 = static_cast<T*>(epi.o1);
-  const int Ym = (Y - 1 + g.NWy) % g.NWy, Zm = (Z - 1 + g.NWz) % g.NWz;
-  auto fbv = [&](int W, int k) {
-    return face[(((int64_t)b * NWG + W) * 3 + i) * FROWS * g.nx + (int64_t)k * g.nx + x];
+  auto fbv = [&](int W, int slot) {
+    return face[((((int64_t)bm * g.NWG + W) * 3 + i) * g.nz + z) * FROWS + slot];
   };
-  T s = o1[o];
-  if (yl == 0) s += fbv(Ym + g.NWy * Z, zl);
-  if (zl == 0) s += fbv(Y + g.NWy * Zm, 15 + yl);
-  if (yl == 0 && zl == 0) s += fbv(Ym + g.NWy * Zm, 14);
-  const double dt = g.prob->dt;
-  if (DIV) {
-    const int qx = x % NQ;  // local index within the element (0 on a shared face)
-    s *= tb->imq[qx] * tb->imq[yl % NQ] * tb->imq[zl % NQ] / (T)(g.hh[0] * g.hh[1] * g.hh[2]);
+  T s;
+  if (yl == 0) {
+    s = o1[o] + fbv(X + g.NX * eym, FB_UY + xl);
+    if (xl == 0) s += fbv(Xm + g.NX * ey, FB_UX) + fbv(Xm + g.NX * eym, FB_UY + 28);
+  } else {
+    s = fbv(L, FB_LX + 4 * (yl - 1) + xl);
+    if (xl == 0) s += fbv(Xm + g.NX * ey, FB_UX + yl);
   }
+  const double dt = g.prob->dt;
+  if (DIV) s *= tb->imq[xl % NQ] * tb->imq[yl] * tb->imq[z % NQ] / (T)(g.hh[0] * g.hh[1] * g.hh[2]);
   T r1 = coef<T>(epi.b1, dt) * s;
   if (epi.x1) r1 += coef<T>(epi.a1, dt) * static_cast<const T*>(epi.x1)[o];
   if (epi.o2) {
@@ -546,8 +544,8 @@ FastArgs make_args(const ProbDev& hp, const ProbDev* dprob) {
   g.nx = hp.n[0];
   g.ny = hp.n[1];
   g.nz = hp.n[2];
-  g.NWy = hp.E[1] / 2;
-  g.NWz = hp.E[2] / 2;
+  g.NX = hp.E[0] / WX;
+  g.NWG = g.NX * hp.E[1];
   for (int k = 0; k < 3; ++k) {
     g.hh[k] = hp.hh[k];
     g.sc[k] = hp.sc[k];
@@ -563,7 +561,7 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
                     const Epi& epi, Coef in_scale, const void* dtab, hipStream_t s) {
   const FastArgs g = make_args(hp, dprob);
   const auto* tb = static_cast<const FastTab<T>*>(dtab);
-  const dim3 grid(g.NWy * g.NWz, hp.batch);
+  const dim3 grid(g.NWG, hp.batch);
   T* fc = static_cast<T*>(face);
   const T* uu = static_cast<const T*>(u);
   const T* vv = static_cast<const T*>(v);
@@ -585,7 +583,7 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
 #undef SEM_FAST_LAUNCH
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = (int64_t)hp.batch * g.NWy * g.NWz * 3 * SROWS * g.nx;
+  const int64_t total = (int64_t)hp.batch * g.NWG * 3 * g.nz * FIXN;
   const unsigned blocks = (unsigned)((total + 255) / 256);
   if (op == OP_JACT)
     hipLaunchKernelGGL((fast3d_fixup<T, false>), dim3(blocks), dim3(256), 0, s, g, tb, fc, epi, hp.batch);
@@ -598,12 +596,12 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
 
 bool fast3d_supported(const ProbDev& hp) {
   // buffer offsets are 32-bit: one batch member (all components, FP64) must stay below 2 GiB
-  return hp.dim == 3 && hp.N == NQ && hp.E[1] % 2 == 0 && hp.E[2] % 2 == 0 && hp.E[0] >= 1 &&
+  return hp.dim == 3 && hp.N == NQ && hp.E[0] % WX == 0 && hp.E[1] >= 1 && hp.E[2] >= 1 &&
          (int64_t)3 * hp.nodes * 8 < ((int64_t)1 << 31);
 }
 
 int64_t fast3d_face_values(const ProbDev& hp) {
-  return (int64_t)hp.batch * (hp.E[1] / 2) * (hp.E[2] / 2) * 3 * FROWS * hp.n[0];
+  return (int64_t)hp.batch * (hp.E[0] / WX) * hp.E[1] * 3 * hp.n[2] * FROWS;
 }
 
 size_t fast3d_table_bytes() { return sizeof(FastTab<double>) + sizeof(FastTab<float>); }

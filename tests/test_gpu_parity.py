@@ -64,8 +64,10 @@ CASES = [
     (2, 6, [3, 3]),
     (3, 7, [3, 2, 4]), (3, 1, [2, 2, 2]), (3, 9, [2, 3, 2]), (3, 4, [1, 2, 3]), (3, 2, [5, 1, 1]),
     (3, 7, [1, 1, 1]), (3, 5, [3, 3, 3]),
-    # order 7 with even element counts in y and z runs the tuned 3-D kernel
-    (3, 7, [1, 2, 2]), (3, 7, [4, 4, 2]), (3, 7, [5, 2, 6]), (3, 7, [2, 6, 4]), (3, 7, [3, 4, 4]),
+    (3, 7, [1, 2, 2]), (3, 7, [5, 2, 6]), (3, 7, [2, 6, 4]),
+    # order 7 with an x element count that is a multiple of 4 runs the tuned 3-D kernel
+    (3, 7, [4, 1, 1]), (3, 7, [4, 2, 3]), (3, 7, [8, 3, 2]), (3, 7, [4, 5, 1]), (3, 7, [12, 1, 2]),
+    (3, 7, [8, 2, 5]), (3, 7, [4, 4, 4]),
 ]
 
 
@@ -80,7 +82,8 @@ def test_operators_fp64(P, dim, N, E):
     assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < TOL_APPLY
 
 
-@pytest.mark.parametrize("dim,N,E", [(1, 8, [16]), (2, 7, [5, 3]), (3, 7, [3, 2, 4]), (3, 5, [2, 2, 3])])
+@pytest.mark.parametrize("dim,N,E", [(1, 8, [16]), (2, 7, [5, 3]), (3, 7, [3, 2, 4]), (3, 5, [2, 2, 3]),
+                                     (3, 7, [4, 2, 3])])
 def test_operators_fp32(P, dim, N, E):
     note(f"operators fp32 dim={dim} N={N} E={E}")
     m, c = make(P, dim, N, E, nu=0.02, dtype=torch.float32)
@@ -94,7 +97,7 @@ def test_operators_fp32(P, dim, N, E):
 @pytest.mark.parametrize("dim,N", [(1, 4), (2, 4), (3, 4), (3, 7)])
 def test_batched_fields(P, dim, N):
     note(f"same-shape batch dim={dim} N={N}")
-    m, c = make(P, dim, N, [3, 2, 2][:dim], nu=0.03, batch=3)
+    m, c = make(P, dim, N, [4, 2, 3][:dim], nu=0.03, batch=3)
     u, v, w = fields(m, 11)
     U, V, W = gpu(u), gpu(v), gpu(w)
     assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
@@ -104,7 +107,7 @@ def test_batched_fields(P, dim, N):
 
 def test_dot_identity_gpu(P):
     note("dot identity on the GPU, 3-D N=7")
-    m, c = make(P, 3, 7, [3, 3, 2], nu=0.01)
+    m, c = make(P, 3, 7, [4, 3, 2], nu=0.01)
     u, v, w = fields(m, 13)
     U, V, W = gpu(u), gpu(v), gpu(w)
     lhs = torch.dot(c.jac_vec(U, V).flatten(), W.flatten()).item()
@@ -193,7 +196,7 @@ def test_c1_trajectory_and_gradient(P):
 
 
 @pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1),
-                                           (3, 7, [3, 2, 4], 1), (3, 7, [2, 2, 2], 2)])
+                                           (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2)])
 def test_rk4_forward_adjoint(P, dim, N, E, batch):
     note(f"RK4 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
     m, c = make(P, dim, N, E, nu=0.01, batch=batch)
