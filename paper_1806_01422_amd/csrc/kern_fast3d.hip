@@ -24,11 +24,12 @@
 //      sweep.  The input plane is carried too, so each step loads 7 new planes.
 //   x: inside a workgroup the shared face of wavefronts w and w + 1 is added through LDS.
 //   workgroup faces: a workgroup owns the nodes x in [28X, 28X + 28), y in [7ey, 7ey + 7).  It
-//      writes its partial sum of the lower y-row (y = 7ey) to the output, and to a face buffer its
-//      contributions to the upper y-row and upper x-column (owned by the neighbours) and the
-//      first 32-byte sector of each of its interior rows (x in [28X, 28X + 4): the x = 28X node
-//      still lacks the left neighbour's part).  fast3d_fixup adds the parts, applies the inverse
-//      mass and the epilogue, and writes those nodes as whole row segments and whole sectors.
+//      writes its finished nodes to the output and, to a face buffer, its partial sums of the
+//      lower y-row (y = 7ey), its contributions to the upper y-row and upper x-column (owned by
+//      the neighbours), and the first 32-byte sector of each interior row (x in [28X, 28X + 4):
+//      the x = 28X node still lacks the left neighbour's part).  fast3d_fixup adds the parts,
+//      applies the inverse mass and the epilogue, and writes those nodes as whole row segments
+//      and whole sectors, so no 32-byte sector of the output is written twice.
 #include "sem_internal.h"
 
 namespace sem {
@@ -36,12 +37,17 @@ namespace {
 
 constexpr int NQ = 7;  // order
 constexpr int WX = 4;  // elements per workgroup along x, one per wavefront
-// Face buffer: per (workgroup, component, grid plane z) FROWS values,
-constexpr int FB_UY = 0;   //   upper y-row y = 7ey + 7, x-local 0..28 (29 values)
-constexpr int FB_UX = 29;  //   upper x-column x = 28X + 28, y-local 0..6 (7 values)
-constexpr int FB_LX = 36;  //   first sector x-local 0..3 of the rows y-local 1..6 (24 values)
-constexpr int FROWS = 60;
-constexpr int FIXN = 52;   // nodes the fixup completes per (workgroup, component, z): 28 + 24
+// Face buffer of one batch member: four regions, each [workgroup][component][grid plane z][width]
+// so that every region is read by one neighbour's fixup as a run contiguous in z.
+//   LY  own lower y-row y = 7ey, x-local 0..27 (partial sums)             width 28
+//   UY  upper y-row y = 7ey + 7, x-local 0..28 (contribution to neighbours) width 29
+//   UX  upper x-column x = 28X + 28, y-local 0..6                          width 7
+//   LX  first sector x-local 0..3 of the rows y-local 1..6                 width 24
+// Region g starts at NWG * 3 * nz * (sum of the widths before it).
+constexpr int W_LY = 28, W_UY = 29, W_UX = 7, W_LX = 24;
+constexpr int O_LY = 0, O_UY = 28, O_UX = 57, O_LX = 64;
+constexpr int FROWS = 88;  // total width
+constexpr int FSEC = 13;   // 32-byte sectors the fixup completes per (workgroup, component, z): 7 + 6
 
 // The even/odd blocks of D are A[i][m] = (D_im - D_i,7-m)/2 and B[i][m] = (D_im + D_i,7-m)/2
 // (i, m < 4).  Centro-antisymmetry makes the blocks of D^T their transposes (A' = B^T, B' = A^T),
@@ -57,6 +63,7 @@ struct FastArgs {
   int Ex, Ey, Ez, nx, ny, nz;
   int NX, NWG;  // workgroups along x (Ex / 4) and per field (NX * Ey)
   double hh[3], sc[3], nu;
+  double ihhh;    // 1 / (h_x h_y h_z)
   int64_t nodes;  // per component
   const ProbDev* prob;
 };
@@ -237,15 +244,15 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   const __amdgpu_buffer_rsrc_t r_x1 = brsrc(EP >= 1 ? static_cast<const T*>(epi.x1) + bo : u, EP >= 1 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_o2 = brsrc(EP >= 2 ? static_cast<T*>(epi.o2) + bo : u, EP >= 2 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_x2 = brsrc(EP >= 2 ? static_cast<const T*>(epi.x2) + bo : u, EP >= 2 ? fbytes : 0);
-  const __amdgpu_buffer_rsrc_t r_fb = brsrc(face + ((int64_t)blockIdx.y * g.NWG + L) * 3 * g.nz * FROWS,
-                                            (uint32_t)(3 * g.nz * FROWS * sizeof(T)));
+  const __amdgpu_buffer_rsrc_t r_fb = brsrc(face + (int64_t)blockIdx.y * g.NWG * 3 * g.nz * FROWS,
+                                            (uint32_t)((int64_t)g.NWG * 3 * g.nz * FROWS * sizeof(T)));
   const double dt = g.prob->dt;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
 
   const int l0 = lane & 7, l1 = lane >> 3;
   const T ihhh = (T)(1.0 / (g.hh[0] * g.hh[1] * g.hh[2]));
-  // quadrature weight omega = (h_x h_y h_z / 8) w_a w_b w_c; with the lane holding the two fixed
-  // indices (l0, l1) and the register the third, the same 8 values serve all three maps
+  // quadrature weight omega = (h_x h_y h_z / 8) w_a w_b w_c (hh = h / 2); with the lane holding
+  // the two fixed indices (l0, l1) and the register the third, the same 8 values serve all maps
   T om[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) om[s] = (T)(g.hh[0] * g.hh[1] * g.hh[2]) * tb->w[l0] * tb->w[l1] * tb->w[s];
@@ -259,17 +266,24 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   const int64_t plane = (int64_t)g.ny * g.nx;
   const int64_t lrow = (int64_t)((7 * ey + l1) % g.ny) * g.nx + (7 * ex + l0) % g.nx;
   // Output roles of the lane's node (7ex + a, 7ey + b, z):
-  //   own   a < 7, b < 7, outside the first sector of an interior row: written here (b = 0: the
-  //         partial sum of the lower y-row, completed by the fixup; b > 0: final value)
-  //   fbk   face-buffer slot (upper y-row, upper x-column, first sectors), -1 if none
+  //   own   finished here: a < 7, 1 <= b < 7, outside the first sector of the row
+  //   face  face-buffer slot (lower and upper y-rows, upper x-column, first sectors), if any
+  //         (a = 7 of wavefronts 0..2 has none: it is added into the next wavefront's a = 0)
   const int a = l0, b = l1;
   const bool lsec = wave == 0 && a < 4 && b >= 1 && b < 7;
-  const bool own = a < 7 && b < 7 && !lsec;
-  const bool partial = b == 0;
-  int fbk = -1;
-  if (b == 7) fbk = a < 7 ? FB_UY + 7 * wave + a : (wave == WX - 1 ? FB_UY + 28 : -1);
-  else if (wave == WX - 1 && a == 7) fbk = FB_UX + b;
-  else if (lsec) fbk = FB_LX + 4 * (b - 1) + a;
+  const bool own = a < 7 && b >= 1 && b < 7 && !lsec;
+  int fo = -1, fw = 0, fk = 0;  // region offset (widths before it), width, index; fo < 0: none
+  if (b == 7) {
+    if (a < 7 || wave == WX - 1) fo = O_UY, fw = W_UY, fk = 7 * wave + a;
+  } else if (a == 7) {
+    if (wave == WX - 1) fo = O_UX, fw = W_UX, fk = b;
+  } else if (b == 0) {
+    fo = O_LY, fw = W_LY, fk = 7 * wave + a;
+  } else if (lsec) {
+    fo = O_LX, fw = W_LX, fk = 4 * (b - 1) + a;
+  }
+  const int64_t fslab = (int64_t)g.NWG * 3 * g.nz;  // values per unit of region width
+  const int64_t flane = fo * fslab + ((int64_t)L * 3 * g.nz) * fw + fk;
   const int64_t orow = (int64_t)(7 * ey + b) * g.nx + 7 * ex + a;  // valid when own
 
   // Load planes c in [c0, 8) of element layer ez (plane 7ez + c, periodic in z).
@@ -289,8 +303,8 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   };
 
   // Write planes c in [c_lo, c_hi) of element layer ez from the summed z-map values Zv: inverse
-  // mass and epilogue for finished nodes, the raw partial sum on the lower y-row, and the
-  // face-buffer slots.  Every lane issues the same stores; inactive ones drop theirs.
+  // mass and epilogue for finished nodes, raw sums to the face-buffer slots.  Every lane issues
+  // the same stores; inactive ones drop theirs.
   auto emit = [&](int ez, const T (&Zv)[3][8], int c_lo, int c_hi, const T (&E1)[3][7], const T (&E2)[3][7]) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -303,10 +317,10 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
         const T sm = (OP != OP_JACT) ? r * (mlane * tb->imq[c]) : r;
         T r1 = b1 * sm;
         if (EP >= 1) r1 += a1 * E1[i][c];
-        bstore(r_o1, (own && inc) ? no : OOB, partial ? r : r1);
-        if (EP >= 2) bstore(r_o2, (own && inc && !partial) ? no : OOB, a2 * E2[i][c] + b2 * sm);
-        const uint32_t fo = (uint32_t)((((int64_t)i * g.nz + z) * FROWS + fbk) * sizeof(T));
-        bstore(r_fb, (fbk >= 0 && inc) ? fo : OOB, r);
+        bstore(r_o1, (own && inc) ? no : OOB, r1);
+        if (EP >= 2) bstore(r_o2, (own && inc) ? no : OOB, a2 * E2[i][c] + b2 * sm);
+        const uint32_t fb = (uint32_t)((flane + ((int64_t)i * g.nz + z) * fw) * sizeof(T));
+        bstore(r_fb, (fo >= 0 && inc) ? fb : OOB, r);
       }
   };
 
@@ -316,27 +330,12 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
 #pragma unroll
       for (int c = 0; c < 7; ++c) {
         const bool inc = c >= c_lo && c < c_hi;
-        const uint32_t no = (own && !partial && inc)
+        const uint32_t no = (own && inc)
                                 ? (uint32_t)((i * g.nodes + (7 * ez + c) * plane + orow) * sizeof(T))
                                 : OOB;
         E1[i][c] = (EP >= 1) ? bload<T>(r_x1, no) : (T)0;
         E2[i][c] = (EP >= 2) ? bload<T>(r_x2, no) : (T)0;
       }
-  };
-
-  // x-map registers -> LDS tile -> z-map registers
-  auto to_zmap = [&](const T (&R)[3][8], T (&Zv)[3][8], T* __restrict__ tile) {
-    wave_sync();
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) tile[i * 512 + tix(q, l0, l1)] = R[i][q];
-    wave_sync();
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int c = 0; c < 8; ++c) Zv[i][c] = tile[i * 512 + tix(l0, l1, c)];
-    wave_sync();
   };
 
   T* __restrict__ tU = sU[wave][0];
@@ -411,8 +410,8 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
           for (int q = 0; q < 8; ++q) tQ[i * 512 + tix(l0, q, l1)] = qv[q] + P[q];
         });
     wave_sync();
-    // ---- x-map (lane (b=l0, c=l1), register a)
-    T R[3][8];
+    // ---- x-map (lane (b=l0, c=l1), register a): accumulate into the tile, keep face a = 7
+    T R7[3];
     map_contrib<T, OP>(
         0,
         [&](int i, T (&Xr)[8]) {
@@ -425,24 +424,32 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
         },
         om, K1x, K2x, tb,
         [&](int i, const T (&P)[8]) {
+          T qv[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) R[i][q] = P[q] + tQ[i * 512 + tix(q, l0, l1)];
+          for (int q = 0; q < 8; ++q) qv[q] = tQ[i * 512 + tix(q, l0, l1)];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) tQ[i * 512 + tix(q, l0, l1)] = qv[q] + P[q];
+          R7[i] = qv[7] + P[7];
         });
     // ---- x-direction summation inside the workgroup: wavefront w's face a = 7 is wavefront
     // w + 1's face a = 0 (double-buffered by step parity: one barrier per step)
     const int par = ez & 1;
     if (wave < WX - 1) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) sEx[par][wave][i][lane] = R[i][7];
+      for (int i = 0; i < 3; ++i) sEx[par][wave][i][lane] = R7[i];
     }
     __syncthreads();
     if (wave > 0) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) R[i][0] += sEx[par][wave - 1][i][lane];
+      for (int i = 0; i < 3; ++i) tQ[i * 512 + tix(0, l0, l1)] += sEx[par][wave - 1][i][lane];
     }
-    // ---- to the z-map; z-direction summation: carry the shared plane to the next layer
+    // ---- read the summed tile in the z-map; z-direction summation: carry the shared plane
+    wave_sync();
     T Zv[3][8];
-    to_zmap(R, Zv, tQ);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) Zv[i][c] = tQ[i * 512 + tix(l0, l1, c)];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       Zv[i][0] += carry[i];
@@ -472,52 +479,64 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
 }
 
 // Completes, for every workgroup (X, ey), component and grid plane z, the nodes of its lower
-// y-row (own partial in o1 plus the lower neighbour's upper-y contribution) and of the first
-// sectors of its interior rows (face-buffer value plus, at x = 28X, the left neighbour's upper-x
-// contribution); the node (28X, 7ey) also receives the diagonal neighbour's corner.  Then the
-// inverse mass (F, J v) and the epilogue.
+// y-row (own partial plus the lower neighbour's upper-y contribution) and of the first sectors of
+// its interior rows (own value plus, at x = 28X, the left neighbour's upper-x contribution); the
+// node (28X, 7ey) also receives the diagonal neighbour's corner.  Then the inverse mass (F, J v)
+// and the epilogue.  One thread per 32-byte output sector (4 nodes along x); blockIdx.x is
+// (workgroup, component), blockIdx.y a range of (z, sector) pairs, blockIdx.z the batch member.
 template <typename T, bool DIV>
 __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>* __restrict__ tb,
-                                                    const T* __restrict__ face, Epi epi, int batch) {
-  const int64_t total = (int64_t)batch * g.NWG * 3 * g.nz * FIXN;
-  int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= total) return;
-  const int k = (int)(t % FIXN);
-  t /= FIXN;
-  const int z = (int)(t % g.nz);
-  t /= g.nz;
-  const int i = (int)(t % 3);
-  t /= 3;
-  const int L = (int)(t % g.NWG);
-  const int bm = (int)(t / g.NWG);
+                                                    const T* __restrict__ face, Epi epi) {
+  const int t = blockIdx.y * 256 + threadIdx.x;
+  if (t >= g.nz * FSEC) return;
+  const int sct = t % FSEC, z = t / FSEC;
+  const int L = blockIdx.x / 3, i = blockIdx.x % 3;
   const int X = L % g.NX, ey = L / g.NX;
-  const int Xm = (X - 1 + g.NX) % g.NX, eym = (ey - 1 + g.Ey) % g.Ey;
-  const int xl = k < 28 ? k : (k - 28) % 4;
-  const int yl = k < 28 ? 0 : 1 + (k - 28) / 4;
-  const int64_t bo = (int64_t)bm * 3 * g.nodes;
-  const int64_t o = bo + i * g.nodes + ((int64_t)z * g.ny + 7 * ey + yl) * g.nx + 7 * WX * X + xl;
-  T* __restrict__ o1 = static_cast<T*>(epi.o1);
-  auto fbv = [&](int W, int slot) {
-    return face[((((int64_t)bm * g.NWG + W) * 3 + i) * g.nz + z) * FROWS + slot];
-  };
-  T s;
+  const int Xm = X == 0 ? g.NX - 1 : X - 1, eym = ey == 0 ? g.Ey - 1 : ey - 1;
+  const int xl0 = sct < 7 ? 4 * sct : 0;
+  const int yl = sct < 7 ? 0 : sct - 6;
+  const int64_t fslab = (int64_t)g.NWG * 3 * g.nz;
+  const T* __restrict__ fm = face + (int64_t)blockIdx.z * fslab * FROWS;
+  // start of (workgroup W, this component, this z) in region (offset o, width w)
+  auto rec = [&](int W, int o, int w) { return fm + o * fslab + (((int64_t)W * 3 + i) * g.nz + z) * w; };
+  T s[4];
   if (yl == 0) {
-    s = o1[o] + fbv(X + g.NX * eym, FB_UY + xl);
-    if (xl == 0) s += fbv(Xm + g.NX * ey, FB_UX) + fbv(Xm + g.NX * eym, FB_UY + 28);
+    const T* __restrict__ own = rec(L, O_LY, W_LY) + xl0;
+    const T* __restrict__ up = rec(X + g.NX * eym, O_UY, W_UY) + xl0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = own[q] + up[q];
+    if (xl0 == 0) s[0] += rec(Xm + g.NX * ey, O_UX, W_UX)[0] + rec(Xm + g.NX * eym, O_UY, W_UY)[28];
   } else {
-    s = fbv(L, FB_LX + 4 * (yl - 1) + xl);
-    if (xl == 0) s += fbv(Xm + g.NX * ey, FB_UX + yl);
+    const T* __restrict__ own = rec(L, O_LX, W_LX) + 4 * (yl - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] = own[q];
+    s[0] += rec(Xm + g.NX * ey, O_UX, W_UX)[yl];
   }
   const double dt = g.prob->dt;
-  if (DIV) s *= tb->imq[xl % NQ] * tb->imq[yl] * tb->imq[z % NQ] / (T)(g.hh[0] * g.hh[1] * g.hh[2]);
-  T r1 = coef<T>(epi.b1, dt) * s;
-  if (epi.x1) r1 += coef<T>(epi.a1, dt) * static_cast<const T*>(epi.x1)[o];
-  if (epi.o2) {
-    T r2 = coef<T>(epi.b2, dt) * s;
-    if (epi.x2) r2 += coef<T>(epi.a2, dt) * static_cast<const T*>(epi.x2)[o];
-    static_cast<T*>(epi.o2)[o] = r2;
+  if (DIV) {
+    const T m = tb->imq[yl] * tb->imq[z % NQ] * (T)g.ihhh;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] *= m * tb->imq[(xl0 + q) % NQ];
   }
-  o1[o] = r1;
+  const int64_t o = (int64_t)blockIdx.z * 3 * g.nodes + i * g.nodes +
+                    ((int64_t)z * g.ny + 7 * ey + yl) * g.nx + 7 * WX * X + xl0;
+  const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
+  // o2 may alias x2 (in-place accumulation): each element is read before it is written
+  T* o1 = static_cast<T*>(epi.o1) + o;
+  const T* x1 = epi.x1 ? static_cast<const T*>(epi.x1) + o : nullptr;
+  T* o2 = epi.o2 ? static_cast<T*>(epi.o2) + o : nullptr;
+  const T* x2 = epi.x2 ? static_cast<const T*>(epi.x2) + o : nullptr;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T r1 = b1 * s[q];
+    if (x1) r1 += a1 * x1[q];
+    if (o2) {
+      T r2 = b2 * s[q];
+      if (x2) r2 += a2 * x2[q];
+      o2[q] = r2;
+    }
+    o1[q] = r1;
+  }
 }
 
 template <typename T>
@@ -551,6 +570,7 @@ FastArgs make_args(const ProbDev& hp, const ProbDev* dprob) {
     g.sc[k] = hp.sc[k];
   }
   g.nu = hp.nu;
+  g.ihhh = 1.0 / (hp.hh[0] * hp.hh[1] * hp.hh[2]);
   g.nodes = hp.nodes;
   g.prob = dprob;
   return g;
@@ -583,12 +603,11 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
 #undef SEM_FAST_LAUNCH
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = (int64_t)hp.batch * g.NWG * 3 * g.nz * FIXN;
-  const unsigned blocks = (unsigned)((total + 255) / 256);
+  const dim3 fgrid((unsigned)(g.NWG * 3), (unsigned)((g.nz * FSEC + 255) / 256), hp.batch);
   if (op == OP_JACT)
-    hipLaunchKernelGGL((fast3d_fixup<T, false>), dim3(blocks), dim3(256), 0, s, g, tb, fc, epi, hp.batch);
+    hipLaunchKernelGGL((fast3d_fixup<T, false>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
   else
-    hipLaunchKernelGGL((fast3d_fixup<T, true>), dim3(blocks), dim3(256), 0, s, g, tb, fc, epi, hp.batch);
+    hipLaunchKernelGGL((fast3d_fixup<T, true>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
   return hipGetLastError();
 }
 
