@@ -97,8 +97,11 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
 
-// swizzled LDS tile index of element-local point (a, b, c)
-__device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b ^ (c & 1)) << 3) + (a ^ b); }
+// Swizzled LDS tile index of element-local point (a, b, c): (c, b ^ c, a ^ b).  In each of the
+// three maps (lanes over (a, b), (a, c) or (b, c)) every group of 32 consecutive lanes hits 32
+// distinct 8-byte bank pairs, so 64-bit accesses are free of bank conflicts with 64 banks (and
+// 32-bit accesses with all 64 lanes at once).
+__device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b ^ c) << 3) + (a ^ b); }
 
 // y = D x (TR = false) or y = D^T x (TR = true) on one 8-point line, even/odd split:
 //   e_m = x_m + x_{7-m}, o_m = x_m - x_{7-m};  y_i = s_i + d_i, y_{7-i} = s_i - d_i  (i < 4)
