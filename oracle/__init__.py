@@ -42,6 +42,11 @@ def lib():
         _lib.orc_rk4_forward.argtypes = [pd, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, dp, dp]
         _lib.orc_rk4_adjoint.argtypes = [pd, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, dp, dp]
         _lib.orc_rk4_tlm.argtypes = [pd, ctypes.c_double, ctypes.c_int32, dp, dp]
+        i32 = ctypes.c_int32
+        _lib.orc_erk_tableau.argtypes = [i32, dp, dp]
+        _lib.orc_erk_forward.argtypes = [pd, i32, ctypes.c_double, i32, i32, dp, dp]
+        _lib.orc_erk_adjoint.argtypes = [pd, i32, ctypes.c_double, i32, i32, dp, dp]
+        _lib.orc_erk_tlm.argtypes = [pd, i32, ctypes.c_double, i32, dp, dp]
         _lib.orc_misfit.argtypes = [pd, dp, dp, dp, dp]
         _lib.orc_coords.argtypes = [pd, ctypes.c_int32, dp]
         _lib.orc_mass.argtypes = [pd, dp]
@@ -168,6 +173,29 @@ class Mesh:
         _check(lib().orc_rk4_tlm(ctypes.byref(self._d), dt, nsteps, _ptr(u), _ptr(du)), "rk4_tlm")
         return u, du
 
+    # General explicit Runge-Kutta by Butcher tableau: scheme "rk4" (classical) or "rk3" (Kutta's
+    # third-order method, the reading taken for the paper's three-stage RK-3).
+    def erk_forward(self, scheme, u0, dt, nsteps, ckpt_every=None):
+        u = self._in(u0).copy()
+        ck = None
+        if ckpt_every:
+            ck = np.zeros((nsteps // ckpt_every,) + u.shape)
+        _check(lib().orc_erk_forward(ctypes.byref(self._d), SCHEMES[scheme], dt, nsteps, ckpt_every or 0, _ptr(u),
+                                      _ptr(ck)), "erk_forward")
+        return u, ck
+
+    def erk_adjoint(self, scheme, ckpt, dt, nsteps, ckpt_every, lamT):
+        lam = self._in(lamT).copy()
+        ck = np.ascontiguousarray(ckpt, dtype=np.float64)
+        _check(lib().orc_erk_adjoint(ctypes.byref(self._d), SCHEMES[scheme], dt, nsteps, ckpt_every, _ptr(ck),
+                                      _ptr(lam)), "erk_adjoint")
+        return lam
+
+    def erk_tlm(self, scheme, u0, du0, dt, nsteps):
+        u, du = self._in(u0).copy(), self._in(du0).copy()
+        _check(lib().orc_erk_tlm(ctypes.byref(self._d), SCHEMES[scheme], dt, nsteps, _ptr(u), _ptr(du)), "erk_tlm")
+        return u, du
+
     def misfit(self, uT, target):
         uT, target = self._in(uT), self._in(target)
         phi = np.zeros(self.batch)
@@ -181,6 +209,18 @@ class Mesh:
         uT, ck = self.rk4_forward(u0, dt, nsteps, ckpt_every)
         phi, lamT = self.misfit(uT, target)
         return phi, self.rk4_adjoint(ck, dt, nsteps, ckpt_every, lamT)
+
+
+SCHEMES = {"rk4": 0, "rk3": 1}
+
+
+def erk_tableau(scheme):
+    """(A, b) of an explicit Runge-Kutta scheme as the oracle uses it."""
+    A, b = np.zeros(16), np.zeros(4)
+    s = lib().orc_erk_tableau(SCHEMES[scheme], _ptr(A), _ptr(b))
+    if s < 0:
+        raise ValueError(scheme)
+    return A[: s * s].reshape(s, s).copy(), b[:s].copy()
 
 
 def num_threads():

@@ -21,6 +21,7 @@
  *   - discrete adjoint of an explicit one-step method          (Sec. 4.1, eqs. adjointloop, initadj,
  *                                                                gradient, adjtime)
  *   - checkpoint-and-recompute of the forward trajectory       (Sec. 5.3, 5.4)
+ *   - the three-stage explicit RK-3 of the scalability runs    (Sec. 6.3), with its adjoint
  *
  * Readings taken where the paper is silent or garbled (listed in the design notes):
  *   * Signs follow the PDE: F = -nu K u - (u.grad)u (the 1-D Jacobian formulas of Sec. 3.2 carry
@@ -595,6 +596,208 @@ int orc_rk4_tlm(const orc_desc* d, double dt, int32_t nsteps, double* u, double*
   for (long b = 0; b < s.m.batch && !rc; ++b)
     for (int k = 0; k < nsteps && !rc; ++k) rc = rk4_tlm_step(&s, dt, u + b * n, du + b * n);
   stepper_free(&s);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* General explicit Runge-Kutta method given by its Butcher tableau (A strictly lower          */
+/* triangular, weights b): stage states U_i = u + dt sum_{j<i} A_ij k_j, k_i = F(U_i),           */
+/* u+ = u + dt sum_i b_i k_i.  The discrete adjoint of that one-step map (Sec. 4.1, applied to  */
+/* a general tableau) runs the stages in reverse:                                               */
+/*     a_i = J(U_i)^T [ dt (b_i lam + sum_{j>i} A_ji a_j) ],   lam <- lam + sum_i a_i,           */
+/* and the tangent-linear map is dk_i = J(U_i)(du + dt sum_{j<i} A_ij dk_j),                     */
+/* du <- du + dt sum_i b_i dk_i.  The paper integrates with a three-stage explicit RK-3 (Sec. 6.3) */
+/* without printing its tableau; scheme 1 takes Kutta's third-order method.  Scheme 0 is the    */
+/* classical RK4 tableau, an independent route to the hand-written RK4 above.                   */
+/* ------------------------------------------------------------------------------------------ */
+#define ERK_MAXS 4
+typedef struct {
+  int s;
+  double A[ERK_MAXS][ERK_MAXS];
+  double b[ERK_MAXS];
+} tableau;
+
+static int erk_tableau(int scheme, tableau* t) {
+  memset(t, 0, sizeof(*t));
+  if (scheme == 0) { /* classical RK4 */
+    t->s = 4;
+    t->A[1][0] = 0.5;
+    t->A[2][1] = 0.5;
+    t->A[3][2] = 1.0;
+    t->b[0] = 1.0 / 6; t->b[1] = 1.0 / 3; t->b[2] = 1.0 / 3; t->b[3] = 1.0 / 6;
+    return 0;
+  }
+  if (scheme == 1) { /* Kutta's third-order method */
+    t->s = 3;
+    t->A[1][0] = 0.5;
+    t->A[2][0] = -1.0; t->A[2][1] = 2.0;
+    t->b[0] = 1.0 / 6; t->b[1] = 2.0 / 3; t->b[2] = 1.0 / 6;
+    return 0;
+  }
+  return -1;
+}
+
+/* host copy of a scheme's tableau: A row-major s x s, b[s]; returns s, or -1 */
+int orc_erk_tableau(int32_t scheme, double* A, double* b) {
+  tableau t;
+  if (erk_tableau(scheme, &t)) return -1;
+  for (int i = 0; i < t.s; ++i) {
+    b[i] = t.b[i];
+    for (int j = 0; j < t.s; ++j) A[i * t.s + j] = t.A[i][j];
+  }
+  return t.s;
+}
+
+typedef struct {
+  mesh m;
+  tableau t;
+  double* Lvec;
+  double *U[ERK_MAXS], *k[ERK_MAXS], *a[ERK_MAXS], *tmp;
+} erk;
+
+static int erk_init(const orc_desc* d, int scheme, erk* r) {
+  memset(r, 0, sizeof(*r));
+  if (erk_tableau(scheme, &r->t)) return -1;
+  if (mesh_init(d, &r->m)) return -1;
+  const long n = r->m.ndof;
+  r->Lvec = malloc(sizeof(double) * r->m.nelem * r->m.C * r->m.nloc);
+  r->tmp = malloc(sizeof(double) * n);
+  if (!r->Lvec || !r->tmp) return -2;
+  for (int i = 0; i < r->t.s; ++i) {
+    r->U[i] = malloc(sizeof(double) * n);
+    r->k[i] = malloc(sizeof(double) * n);
+    r->a[i] = malloc(sizeof(double) * n);
+    if (!r->U[i] || !r->k[i] || !r->a[i]) return -2;
+  }
+  return 0;
+}
+static void erk_free(erk* r) {
+  free(r->Lvec); free(r->tmp);
+  for (int i = 0; i < ERK_MAXS; ++i) { free(r->U[i]); free(r->k[i]); free(r->a[i]); }
+}
+
+/* stage states U_i and stage slopes k_i of one step from u */
+static int erk_stages(erk* r, double dt, const double* u) {
+  const long n = r->m.ndof;
+  int rc = 0;
+  for (int i = 0; i < r->t.s; ++i) {
+    for (long g = 0; g < n; ++g) {
+      double acc = 0.0;
+      for (int j = 0; j < i; ++j) acc += r->t.A[i][j] * r->k[j][g];
+      r->U[i][g] = u[g] + dt * acc;
+    }
+    rc |= apply_one(&r->m, OP_RHS, r->U[i], NULL, r->k[i], r->Lvec);
+  }
+  return rc;
+}
+
+static int erk_step(erk* r, double dt, double* u) {
+  if (erk_stages(r, dt, u)) return -2;
+  for (long g = 0; g < r->m.ndof; ++g) {
+    double acc = 0.0;
+    for (int i = 0; i < r->t.s; ++i) acc += r->t.b[i] * r->k[i][g];
+    u[g] += dt * acc;
+  }
+  return 0;
+}
+
+static int erk_adjoint_step(erk* r, double dt, const double* u, double* lam) {
+  const long n = r->m.ndof;
+  int rc = 0;
+  if (erk_stages(r, dt, u)) return -2;
+  for (int i = r->t.s - 1; i >= 0; --i) {
+    for (long g = 0; g < n; ++g) {
+      double acc = r->t.b[i] * lam[g];
+      for (int j = i + 1; j < r->t.s; ++j) acc += r->t.A[j][i] * r->a[j][g];
+      r->tmp[g] = dt * acc;
+    }
+    rc |= apply_one(&r->m, OP_JACT, r->U[i], r->tmp, r->a[i], r->Lvec);
+  }
+  for (long g = 0; g < n; ++g)
+    for (int i = 0; i < r->t.s; ++i) lam[g] += r->a[i][g];
+  return rc;
+}
+
+static int erk_tlm_step(erk* r, double dt, double* u, double* du) {
+  const long n = r->m.ndof;
+  int rc = 0;
+  if (erk_stages(r, dt, u)) return -2;
+  double** dk = r->a; /* reused as the stage derivatives */
+  for (int i = 0; i < r->t.s; ++i) {
+    for (long g = 0; g < n; ++g) {
+      double acc = 0.0;
+      for (int j = 0; j < i; ++j) acc += r->t.A[i][j] * dk[j][g];
+      r->tmp[g] = du[g] + dt * acc;
+    }
+    rc |= apply_one(&r->m, OP_JAC, r->U[i], r->tmp, dk[i], r->Lvec);
+  }
+  for (long g = 0; g < n; ++g) {
+    double acc = 0.0, accu = 0.0;
+    for (int i = 0; i < r->t.s; ++i) {
+      acc += r->t.b[i] * dk[i][g];
+      accu += r->t.b[i] * r->k[i][g];
+    }
+    du[g] += dt * acc;
+    u[g] += dt * accu;
+  }
+  return rc;
+}
+
+/* Forward trajectory with checkpoints, as orc_rk4_forward, for any tableau. */
+int orc_erk_forward(const orc_desc* d, int32_t scheme, double dt, int32_t nsteps, int32_t K, double* u,
+                    double* ckpt) {
+  if (nsteps < 0 || (ckpt && (K < 1 || nsteps % K))) return -1;
+  erk r;
+  int rc = erk_init(d, scheme, &r);
+  if (rc) { erk_free(&r); return rc; }
+  const long n = r.m.ndof, B = r.m.batch;
+  for (long b = 0; b < B && !rc; ++b) {
+    double* ub = u + b * n;
+    for (int k = 0; k < nsteps && !rc; ++k) {
+      if (ckpt && k % K == 0) memcpy(ckpt + ((long)(k / K) * B + b) * n, ub, sizeof(double) * n);
+      rc = erk_step(&r, dt, ub);
+    }
+  }
+  erk_free(&r);
+  return rc;
+}
+
+/* Discrete adjoint with uniform checkpoints and segment recompute, as orc_rk4_adjoint. */
+int orc_erk_adjoint(const orc_desc* d, int32_t scheme, double dt, int32_t nsteps, int32_t K, const double* ckpt,
+                    double* lam) {
+  if (nsteps < 0 || K < 1 || nsteps % K) return -1;
+  erk r;
+  int rc = erk_init(d, scheme, &r);
+  if (rc) { erk_free(&r); return rc; }
+  const long n = r.m.ndof, B = r.m.batch;
+  double* seg = malloc(sizeof(double) * n * (size_t)K);
+  if (!seg) { erk_free(&r); return -2; }
+  for (long b = 0; b < B && !rc; ++b) {
+    double* lb = lam + b * n;
+    for (int sg = nsteps / K - 1; sg >= 0 && !rc; --sg) {
+      memcpy(seg, ckpt + ((long)sg * B + b) * n, sizeof(double) * n);
+      for (int k = 1; k < K && !rc; ++k) {
+        memcpy(seg + k * n, seg + (k - 1) * n, sizeof(double) * n);
+        rc = erk_step(&r, dt, seg + k * n);
+      }
+      for (int k = K - 1; k >= 0 && !rc; --k) rc = erk_adjoint_step(&r, dt, seg + k * n, lb);
+    }
+  }
+  free(seg);
+  erk_free(&r);
+  return rc;
+}
+
+/* Tangent-linear trajectory for any tableau. */
+int orc_erk_tlm(const orc_desc* d, int32_t scheme, double dt, int32_t nsteps, double* u, double* du) {
+  if (nsteps < 0) return -1;
+  erk r;
+  int rc = erk_init(d, scheme, &r);
+  if (rc) { erk_free(&r); return rc; }
+  const long n = r.m.ndof;
+  for (long b = 0; b < r.m.batch && !rc; ++b)
+    for (int k = 0; k < nsteps && !rc; ++k) rc = erk_tlm_step(&r, dt, u + b * n, du + b * n);
+  erk_free(&r);
   return rc;
 }
 

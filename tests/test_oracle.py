@@ -431,3 +431,104 @@ def test_invalid_arguments_rejected():
     with pytest.raises(RuntimeError):
         m = mesh(1, 3, [2])
         m.rk4_adjoint(np.zeros((3,) + m.shape), 1e-3, 10, 3, np.zeros(m.shape))
+
+
+# ------------------------------------------------------------------------------------------------
+# General explicit Runge-Kutta (the paper's three-stage RK-3 of Sec. 6.3; Kutta's tableau is the
+# reading taken, the paper prints none) and its discrete adjoint (Sec. 4.1 for a general tableau)
+# ------------------------------------------------------------------------------------------------
+def test_rk3_tableau_is_three_stage_third_order():
+    A, b = oracle.erk_tableau("rk3")
+    c = A.sum(axis=1)
+    assert A.shape == (3, 3) and np.allclose(np.triu(A), 0)  # three explicit stages
+    # the four order conditions of a third-order Runge-Kutta method
+    assert abs(b.sum() - 1) < 1e-15
+    assert abs(b @ c - 1 / 2) < 1e-15
+    assert abs(b @ c ** 2 - 1 / 3) < 1e-15
+    assert abs(b @ (A @ c) - 1 / 6) < 1e-15
+
+
+def test_rk3_third_order_in_dt():
+    nu, a, T = 0.1, 1.25, 0.5
+    m = oracle.Mesh(1, 8, [4], [4.0], nu)
+    u0 = cole_hopf(m.coords(0), 0.0, nu, a)[None, None]
+    ref, _ = m.rk4_forward(u0, 2.5e-4, 2000)
+    errs = []
+    for dt in (0.01, 0.005, 0.0025):
+        uT, _ = m.erk_forward("rk3", u0, dt, int(round(T / dt)))
+        errs.append(rel(uT, ref))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(2.7 < r < 3.3 for r in rates), (errs, rates)
+
+
+def test_generic_tableau_route_reproduces_rk4():
+    # the general explicit-RK code with the classical tableau against the separately pinned RK4
+    m = mesh(2, 5, [3, 2], nu=0.01)
+    u0 = wl.fourier_field([m.coords(0), m.coords(1)], [1, 1], 3, 21)[None]
+    lamT = rand(m, 22)
+    dt, n, K = 1e-3, 8, 4
+    a, cka = m.rk4_forward(u0, dt, n, K)
+    b, ckb = m.erk_forward("rk4", u0, dt, n, K)
+    assert rel(b, a) < 1e-15 and rel(ckb, cka) < 1e-15
+    assert rel(m.erk_adjoint("rk4", ckb, dt, n, K, lamT), m.rk4_adjoint(cka, dt, n, K, lamT)) < 1e-14
+
+
+def test_rk3_adjoint_gradient_vs_finite_differences():
+    m, u0, target = c1_inputs()
+    dt, n, K = wl.C1_DT, wl.C1_STEPS, 10
+    uT, ck = m.erk_forward("rk3", u0, dt, n, K)
+    _, lamT = m.misfit(uT, target)
+    g = m.erk_adjoint("rk3", ck, dt, n, K, lamT)
+
+    def Phi(u):
+        return m.misfit(m.erk_forward("rk3", u, dt, n)[0], target)[0][0]
+
+    for s in range(8):
+        d = wl.normal_field(m.shape, 300 + s)
+        eps = 1e-4 * np.linalg.norm(u0) / np.linalg.norm(d)
+        fd = (8 * (Phi(u0 + eps * d) - Phi(u0 - eps * d)) - (Phi(u0 + 2 * eps * d) - Phi(u0 - 2 * eps * d))) \
+            / (12 * eps)
+        ad = np.vdot(g, d)
+        assert abs(fd - ad) <= 1e-8 * abs(ad), (s, fd, ad)
+
+
+def test_rk3_tangent_linear_adjoint_duality():
+    m = mesh(2, 5, [3, 3], nu=0.01)
+    u0 = wl.fourier_field([m.coords(0), m.coords(1)], [1, 1], 3, 9)[None]
+    du0, lamN = rand(m, 10), rand(m, 11)
+    dt, n, K = 1e-3, 12, 4
+    _, duN = m.erk_tlm("rk3", u0, du0, dt, n)
+    _, ck = m.erk_forward("rk3", u0, dt, n, K)
+    lam0 = m.erk_adjoint("rk3", ck, dt, n, K, lamN)
+    a, b = np.vdot(lam0, du0), np.vdot(lamN, duN)
+    assert abs(a - b) < 1e-12 * abs(b)
+
+
+def test_rk3_frozen_speed_advection_diffusion():
+    # the linear problem of test_frozen_speed_advection_diffusion, stepped with RK-3
+    nu, T, dt, dim = 1e-3, 0.05, 5e-4, 1
+    amp = wl.rng(4).uniform(0.9, 1.0, 5)
+    m = mesh(dim, 12, [6], nu=nu)
+    X = grids(m)
+
+    def exact(t):
+        s = 0.0
+        for j, aj in enumerate(amp[:3], start=1):
+            s = s + aj * np.sin(2 * np.pi * j * (X[0] - 0.1 * t)) * np.exp(-nu * 4 * np.pi ** 2 * j * j * t)
+        return s[None, None]
+
+    ubar = np.full((1, 1) + X[0].shape, 0.1)
+    _, vT = m.erk_tlm("rk3", ubar, exact(0.0), dt, int(round(T / dt)))
+    assert rel(vT, exact(T)) < 1e-7
+
+
+def test_rk3_checkpointing_is_bitwise_store_all():
+    m, u0, target = c1_inputs()
+    dt, n = wl.C1_DT, 20
+    lams = []
+    for K in (1, 5, 20):
+        uT, ck = m.erk_forward("rk3", u0, dt, n, K)
+        _, lamT = m.misfit(uT, target)
+        lams.append(m.erk_adjoint("rk3", ck, dt, n, K, lamT))
+    np.testing.assert_array_equal(lams[0], lams[1])
+    np.testing.assert_array_equal(lams[0], lams[2])
