@@ -208,6 +208,9 @@ def main():
     t_jv = event_time_ms(lambda: ctx.jac_vec(U, V, JV), reps)
     bytes_jt = 24.0 * dof  # read u and w, write J^T w (FP64)
     achieved = bytes_jt / (t_jt / 1e3) / 1e9
+    # reference: a plain elementwise streaming kernel over one field (read 8 B, write 8 B per DOF)
+    t_copy = event_time_ms(lambda: torch.neg(U, out=JV), reps)
+    copy_gbs = 16.0 * dof / (t_copy / 1e3) / 1e9
     out = {
         "metric": "GDOF/s for F(u) and J^T w (FP64), J^T/F cost ratio, gradient/s batched vs plain",
         "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -224,6 +227,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic()},
         "f_hbm_frac": round(16.0 * dof / (t_f / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "stream_copy": {"gbs": round(copy_gbs, 1), "jt_frac": round(achieved / copy_gbs, 4),
+                        "f_frac": round(16.0 * dof / (t_f / 1e3) / 1e9 / copy_gbs, 4)},
     }
     if args.calib_copy:
         # A plain copy of one field (read 8 B, write 8 B per DOF): the reference dispatch against

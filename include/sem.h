@@ -45,6 +45,11 @@ typedef enum {
 
 typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
 
+/* Explicit time integrators.  SEM_RK4: the classical four-stage method.  SEM_RK3: the three-stage
+   explicit RK-3 of the paper's scalability runs (Sec. 6.3), which prints no tableau; libsem takes
+   Kutta's third-order method (c = 0, 1/2, 1; a21 = 1/2, a31 = -1, a32 = 2; b = 1/6, 2/3, 1/6). */
+typedef enum { SEM_RK4 = 0, SEM_RK3 = 1 } sem_scheme;
+
 /* Problem descriptor.  Supported: dim 1..3; order 1..12 for dim 1 and 2, 1..9 for dim 3;
    elems[k] >= 1; length[k] > 0; nu >= 0; batch >= 1.  Entries past dim are ignored. */
 typedef struct {
@@ -101,7 +106,15 @@ int sem_rk4_forward(sem_ctx ctx, void* u, double dt, int32_t nsteps, int32_t ckp
    recomputed (3 F) and four J^T products are applied. */
 int sem_rk4_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every,
                     void* lam, void* work);
-/* Bytes of caller work buffer needed by sem_rk4_adjoint for a given ckpt_every. */
+/* The same two calls for any sem_scheme: the stage updates of every scheme are fused into the
+   summation kernels and one step is a captured graph.  RK-3: a step applies F three times; its
+   discrete adjoint (Sec. 4.1 for a general tableau: a_i = J(U_i)^T dt (b_i lam + sum_{j>i} A_ji a_j),
+   lam <- lam + sum_i a_i) recomputes two stage states (2 F) and applies three J^T.  ckpt, work and
+   errors as for RK4; an unknown scheme is SEM_ERR_ARG. */
+int sem_rk_forward(sem_ctx ctx, int32_t scheme, void* u, double dt, int32_t nsteps, int32_t ckpt_every, void* ckpt);
+int sem_rk_adjoint(sem_ctx ctx, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every,
+                   void* lam, void* work);
+/* Bytes of caller work buffer needed by sem_rk4_adjoint / sem_rk_adjoint for a given ckpt_every. */
 int sem_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, int64_t* bytes);
 /* Enable (1) or disable (0, default) the non-finite check at the end of sem_rk4_forward (one
    host synchronisation per call). */
@@ -134,6 +147,10 @@ int sem_batch_rk4_forward(sem_batch b, void* u, int32_t nsteps, int32_t ckpt_eve
 /* Discrete adjoint for every problem; work must hold sem_batch_workspace_bytes bytes. */
 int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t ckpt_every, void* lam,
                           void* work);
+/* The same for any sem_scheme. */
+int sem_batch_rk_forward(sem_batch b, int32_t scheme, void* u, int32_t nsteps, int32_t ckpt_every, void* ckpt);
+int sem_batch_rk_adjoint(sem_batch b, int32_t scheme, const void* ckpt, int32_t nsteps, int32_t ckpt_every,
+                         void* lam, void* work);
 int sem_batch_workspace_bytes(sem_batch b, int32_t ckpt_every, int64_t* bytes);
 /* Launch shape of the element stage.  persistent = 1: one persistent launch over all problems
    (2-D sets of more than one problem) with `param` workgroups walking a cost-sorted work list;

@@ -224,7 +224,7 @@ __device__ __forceinline__ int logical_wg(int bid, int nwg) {
 }
 
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
-// 2 = additionally o2 = a2 x2 + b2 s.
+// 2 = o1 = a1 x1 + c1 x2 + b1 s and (when o2 is given) o2 = a2 x2 + c2 x1 + b2 s.
 template <typename T, int OP, int EP>
 __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                      const T* __restrict__ u, const T* __restrict__ v,
@@ -244,13 +244,16 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   const T* __restrict__ vb = HASV ? v + bo : nullptr;
   const uint32_t fbytes = (uint32_t)(3 * g.nodes * sizeof(T));  // one batch member, all components
   const __amdgpu_buffer_rsrc_t r_o1 = brsrc(static_cast<T*>(epi.o1) + bo, fbytes);
-  const __amdgpu_buffer_rsrc_t r_x1 = brsrc(EP >= 1 ? static_cast<const T*>(epi.x1) + bo : u, EP >= 1 ? fbytes : 0);
-  const __amdgpu_buffer_rsrc_t r_o2 = brsrc(EP >= 2 ? static_cast<T*>(epi.o2) + bo : u, EP >= 2 ? fbytes : 0);
-  const __amdgpu_buffer_rsrc_t r_x2 = brsrc(EP >= 2 ? static_cast<const T*>(epi.x2) + bo : u, EP >= 2 ? fbytes : 0);
+  // a missing operand gets an empty range: its loads return 0 and its stores are dropped
+  const bool hx1 = EP >= 1 && epi.x1, ho2 = EP >= 2 && epi.o2, hx2 = EP >= 2 && epi.x2;
+  const __amdgpu_buffer_rsrc_t r_x1 = brsrc(hx1 ? static_cast<const T*>(epi.x1) + bo : u, hx1 ? fbytes : 0);
+  const __amdgpu_buffer_rsrc_t r_o2 = brsrc(ho2 ? static_cast<T*>(epi.o2) + bo : u, ho2 ? fbytes : 0);
+  const __amdgpu_buffer_rsrc_t r_x2 = brsrc(hx2 ? static_cast<const T*>(epi.x2) + bo : u, hx2 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_fb = brsrc(face + (int64_t)blockIdx.y * g.NWG * 3 * g.nz * FROWS,
                                             (uint32_t)((int64_t)g.NWG * 3 * g.nz * FROWS * sizeof(T)));
   const double dt = g.prob->dt;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
+  const T c1 = coef<T>(epi.c1, dt), c2 = coef<T>(epi.c2, dt);
 
   const int l0 = lane & 7, l1 = lane >> 3;
   const T ihhh = (T)(1.0 / (g.hh[0] * g.hh[1] * g.hh[2]));
@@ -320,8 +323,9 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
         const T sm = (OP != OP_JACT) ? r * (mlane * tb->imq[c]) : r;
         T r1 = b1 * sm;
         if (EP >= 1) r1 += a1 * E1[i][c];
+        if (EP >= 2) r1 += c1 * E2[i][c];
         bstore(r_o1, (own && inc) ? no : OOB, r1);
-        if (EP >= 2) bstore(r_o2, (own && inc) ? no : OOB, a2 * E2[i][c] + b2 * sm);
+        if (EP >= 2) bstore(r_o2, (own && inc) ? no : OOB, a2 * E2[i][c] + c2 * E1[i][c] + b2 * sm);
         const uint32_t fb = (uint32_t)((flane + ((int64_t)i * g.nz + z) * fw) * sizeof(T));
         bstore(r_fb, (fo >= 0 && inc) ? fb : OOB, r);
       }
@@ -524,6 +528,7 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   const int64_t o = (int64_t)blockIdx.z * 3 * g.nodes + i * g.nodes +
                     ((int64_t)z * g.ny + 7 * ey + yl) * g.nx + 7 * WX * X + xl0;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
+  const T c1 = coef<T>(epi.c1, dt), c2 = coef<T>(epi.c2, dt);
   // o2 may alias x2 (in-place accumulation): each element is read before it is written
   T* o1 = static_cast<T*>(epi.o1) + o;
   const T* x1 = epi.x1 ? static_cast<const T*>(epi.x1) + o : nullptr;
@@ -531,13 +536,9 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   const T* x2 = epi.x2 ? static_cast<const T*>(epi.x2) + o : nullptr;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    T r1 = b1 * s[q];
-    if (x1) r1 += a1 * x1[q];
-    if (o2) {
-      T r2 = b2 * s[q];
-      if (x2) r2 += a2 * x2[q];
-      o2[q] = r2;
-    }
+    const T v1 = x1 ? x1[q] : (T)0, v2 = x2 ? x2[q] : (T)0;
+    T r1 = b1 * s[q] + a1 * v1 + c1 * v2;
+    if (o2) o2[q] = b2 * s[q] + a2 * v2 + c2 * v1;
     o1[q] = r1;
   }
 }
@@ -588,7 +589,7 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
   T* fc = static_cast<T*>(face);
   const T* uu = static_cast<const T*>(u);
   const T* vv = static_cast<const T*>(v);
-  const int ep = epi.o2 ? 2 : (epi.x1 ? 1 : 0);
+  const int ep = (epi.o2 || epi.x2) ? 2 : (epi.x1 ? 1 : 0);
 #define SEM_FAST_LAUNCH(OPV, EPV)                                                                           \
   hipLaunchKernelGGL((fast3d_kernel<T, OPV, EPV>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale)
 #define SEM_FAST_EP(OPV)          \

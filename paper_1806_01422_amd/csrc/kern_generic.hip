@@ -303,6 +303,7 @@ __global__ __launch_bounds__(256) void dss_kernel(const ProbDev* __restrict__ pr
   const double dt = pr->dt;
   const T b1 = (T)(epi.b1.c0 + epi.b1.cdt * dt), a1 = (T)(epi.a1.c0 + epi.a1.cdt * dt);
   const T b2 = (T)(epi.b2.c0 + epi.b2.cdt * dt), a2 = (T)(epi.a2.c0 + epi.a2.cdt * dt);
+  const T c1 = (T)(epi.c1.c0 + epi.c1.cdt * dt), c2 = (T)(epi.c2.c0 + epi.c2.cdt * dt);
   const int64_t ob = pr->off + b * DIM * pr->nodes + g;
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
@@ -316,14 +317,11 @@ __global__ __launch_bounds__(256) void dss_kernel(const ProbDev* __restrict__ pr
         }
     if (DIV) s = s / (T)mass;
     const int64_t o = ob + c * pr->nodes;
-    T r1 = b1 * s;
-    if (epi.x1) r1 += a1 * static_cast<const T*>(epi.x1)[o];
-    if (epi.o2) {
-      T r2 = b2 * s;
-      if (epi.x2) r2 += a2 * static_cast<const T*>(epi.x2)[o];
-      static_cast<T*>(epi.o2)[o] = r2;
-    }
-    static_cast<T*>(epi.o1)[o] = r1;
+    // o2 may alias x2: both operands are read before either output is written
+    const T v1 = epi.x1 ? static_cast<const T*>(epi.x1)[o] : (T)0;
+    const T v2 = epi.x2 ? static_cast<const T*>(epi.x2)[o] : (T)0;
+    if (epi.o2) static_cast<T*>(epi.o2)[o] = b2 * s + a2 * v2 + c2 * v1;
+    static_cast<T*>(epi.o1)[o] = b1 * s + a1 * v1 + c1 * v2;
   }
 }
 

@@ -335,28 +335,71 @@ struct Integrator {
   size_t ts = 8;
   enum { STATE, S1, S2, ACC, USTATE, A2, A3, A4, T1, T2, LACC, LAMB, NBUF };
   DevBuf buf[NBUF];
-  bool ready = false;
+  static constexpr int NSCHEME = 2;  // SEM_RK4, SEM_RK3
+  bool ready[NSCHEME] = {};
   hipStream_t cap = nullptr;
-  hipGraphExec_t gstep = nullptr, gadj = nullptr;
+  hipGraphExec_t gstep[NSCHEME] = {}, gadj[NSCHEME] = {};
   DevBuf dts;  // per-problem dt table for the batch
 
   ~Integrator() {
-    if (gstep) (void)hipGraphExecDestroy(gstep);
-    if (gadj) (void)hipGraphExecDestroy(gadj);
+    reset_graphs();
     if (cap) (void)hipStreamDestroy(cap);
   }
   void* b(int i) { return buf[i].p; }
 
   // drop the captured graphs (after the operator's launch configuration changed)
   void reset_graphs() {
-    if (gstep) (void)hipGraphExecDestroy(gstep);
-    if (gadj) (void)hipGraphExecDestroy(gadj);
-    gstep = gadj = nullptr;
-    ready = false;
+    for (int k = 0; k < NSCHEME; ++k) {
+      if (gstep[k]) (void)hipGraphExecDestroy(gstep[k]);
+      if (gadj[k]) (void)hipGraphExecDestroy(gadj[k]);
+      gstep[k] = gadj[k] = nullptr;
+      ready[k] = false;
+    }
+  }
+
+  hipError_t enqueue_step(hipStream_t s, int scheme) {
+    return scheme == SEM_RK3 ? enqueue_step_rk3(s) : enqueue_step_rk4(s);
+  }
+  hipError_t enqueue_adjoint_step(hipStream_t s, int scheme) {
+    return scheme == SEM_RK3 ? enqueue_adjoint_step_rk3(s) : enqueue_adjoint_step_rk4(s);
+  }
+
+  // one step of Kutta's third-order method on STATE, stage updates fused into the epilogues:
+  //   U2 = u + dt/2 k1,  U3 = u - dt k1 + 2 dt k2 = 3u - 2 U2 + 2 dt k2,
+  //   u+ = u + dt/6 k1 + 2dt/3 k2 + dt/6 k3 = [(2/3) u + (1/3) U2 + (2dt/3) k2] + dt/6 k3
+  hipError_t enqueue_step_rk3(hipStream_t s) {
+    hipError_t e;
+    const Coef one{1, 0}, zero{0, 0};
+    Epi ep{b(S1), b(STATE), one, {0, 0.5}, nullptr, nullptr, zero, zero};
+    if ((e = os->apply(OP_RHS, b(STATE), nullptr, one, ep, s))) return e;
+    ep = Epi{b(S2), b(STATE), {3, 0}, {0, 2.0}, b(ACC), b(S1), {1.0 / 3, 0}, {0, 2.0 / 3}, {-2, 0}, {2.0 / 3, 0}};
+    if ((e = os->apply(OP_RHS, b(S1), nullptr, one, ep, s))) return e;
+    ep = Epi{b(STATE), b(ACC), one, {0, 1.0 / 6}, nullptr, nullptr, zero, zero};
+    return os->apply(OP_RHS, b(S2), nullptr, one, ep, s);
+  }
+
+  // reverse sweep through one step of Kutta's method taken from USTATE (tableau A21 = 1/2,
+  // A31 = -1, A32 = 2, b = 1/6, 2/3, 1/6), updating LAMB in place:
+  //   a3 = J(U3)^T (dt/6 lam);  a2 = J(U2)^T (2dt/3 lam + 2 dt a3);
+  //   a1 = J(u)^T (dt/6 lam + dt/2 a2 - dt a3);  lam <- lam + a1 + a2 + a3.
+  // With S = lam + a3 kept in LACC, the input of a1 is (7dt/6) lam - dt S + dt/2 a2.
+  hipError_t enqueue_adjoint_step_rk3(hipStream_t s) {
+    hipError_t e;
+    const Coef one{1, 0}, zero{0, 0};
+    Epi ep{b(A2), b(USTATE), one, {0, 0.5}, nullptr, nullptr, zero, zero};
+    if ((e = os->apply(OP_RHS, b(USTATE), nullptr, one, ep, s))) return e;
+    ep = Epi{b(A3), b(USTATE), {3, 0}, {0, 2.0}, nullptr, b(A2), zero, zero, {-2, 0}, zero};
+    if ((e = os->apply(OP_RHS, b(A2), nullptr, one, ep, s))) return e;
+    ep = Epi{b(T1), b(LAMB), {0, 2.0 / 3}, {0, 2.0}, b(LACC), b(LAMB), one, one};
+    if ((e = os->apply(OP_JACT, b(A3), b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
+    ep = Epi{b(T2), b(LAMB), {0, 7.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one, {0, -1.0}, zero};
+    if ((e = os->apply(OP_JACT, b(A2), b(T1), one, ep, s))) return e;
+    ep = Epi{b(LAMB), b(LACC), one, one, nullptr, nullptr, zero, zero};
+    return os->apply(OP_JACT, b(USTATE), b(T2), one, ep, s);
   }
 
   // one RK4 step on STATE (stage updates fused into the summation epilogues)
-  hipError_t enqueue_step(hipStream_t s) {
+  hipError_t enqueue_step_rk4(hipStream_t s) {
     hipError_t e;
     Epi ep{};
     // k1 = F(u):  S1 = u + dt/2 k1;  ACC = u + dt/6 k1
@@ -377,7 +420,7 @@ struct Integrator {
   //   U2 = u + dt/2 F(u), U3 = u + dt/2 F(U2), U4 = u + dt F(U3)   (recomputed)
   //   a4 = J(U4)^T (dt/6 lam); a3 = J(U3)^T (dt/3 lam + dt a4); a2 = J(U2)^T (dt/3 lam + dt/2 a3);
   //   a1 = J(u)^T (dt/6 lam + dt/2 a2); lam <- lam + a1 + a2 + a3 + a4
-  hipError_t enqueue_adjoint_step(hipStream_t s) {
+  hipError_t enqueue_adjoint_step_rk4(hipStream_t s) {
     hipError_t e;
     const Coef one{1, 0}, zero{0, 0};
     Epi ep{b(A2), b(USTATE), one, {0, 0.5}, nullptr, nullptr, zero, zero};
@@ -396,8 +439,8 @@ struct Integrator {
     return os->apply(OP_JACT, b(USTATE), b(T1), one, ep, s);
   }
 
-  int prepare() {
-    if (ready) return SEM_OK;
+  int prepare(int scheme) {
+    if (ready[scheme]) return SEM_OK;
     for (int i = 0; i < NBUF; ++i) {
       if (buf[i].p) continue;
       int rc = buf[i].alloc(n * ts);
@@ -406,27 +449,27 @@ struct Integrator {
     if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_step(cap);
+    hipError_t e = enqueue_step(cap, scheme);
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return fail(SEM_ERR_HIP, "capturing the RK4 step: %s", hipGetErrorString(e ? e : e2));
+      return fail(SEM_ERR_HIP, "capturing the time step: %s", hipGetErrorString(e ? e : e2));
     }
-    e = hipGraphInstantiate(&gstep, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&gstep[scheme], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HIPCHK(e);
     g = nullptr;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    e = enqueue_adjoint_step(cap);
+    e = enqueue_adjoint_step(cap, scheme);
     e2 = hipStreamEndCapture(cap, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return fail(SEM_ERR_HIP, "capturing the RK4 adjoint step: %s", hipGetErrorString(e ? e : e2));
+      return fail(SEM_ERR_HIP, "capturing the adjoint step: %s", hipGetErrorString(e ? e : e2));
     }
-    e = hipGraphInstantiate(&gadj, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&gadj[scheme], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     HIPCHK(e);
-    ready = true;
+    ready[scheme] = true;
     return SEM_OK;
   }
 
@@ -439,20 +482,20 @@ struct Integrator {
     return SEM_OK;
   }
 
-  int forward(void* u, int32_t nsteps, int32_t K, void* ckpt, hipStream_t s) {
+  int forward(int scheme, void* u, int32_t nsteps, int32_t K, void* ckpt, hipStream_t s) {
     const size_t bytes = n * ts;
     HIPCHK(hipMemcpyAsync(b(STATE), u, bytes, hipMemcpyDeviceToDevice, s));
     for (int k = 0; k < nsteps; ++k) {
       if (ckpt && k % K == 0)
         HIPCHK(hipMemcpyAsync(static_cast<char*>(ckpt) + (size_t)(k / K) * bytes, b(STATE), bytes,
                               hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipGraphLaunch(gstep, s));
+      HIPCHK(hipGraphLaunch(gstep[scheme], s));
     }
     HIPCHK(hipMemcpyAsync(u, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
     return SEM_OK;
   }
 
-  int adjoint(const void* ckpt, int32_t nsteps, int32_t K, void* lam, void* work, hipStream_t s) {
+  int adjoint(int scheme, const void* ckpt, int32_t nsteps, int32_t K, void* lam, void* work, hipStream_t s) {
     const size_t bytes = n * ts;
     char* wk = static_cast<char*>(work);
     HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
@@ -461,12 +504,12 @@ struct Integrator {
                             hipMemcpyDeviceToDevice, s));
       HIPCHK(hipMemcpyAsync(wk, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
       for (int k = 1; k < K; ++k) {
-        HIPCHK(hipGraphLaunch(gstep, s));
+        HIPCHK(hipGraphLaunch(gstep[scheme], s));
         HIPCHK(hipMemcpyAsync(wk + (size_t)k * bytes, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
       }
       for (int k = K - 1; k >= 0; --k) {
         HIPCHK(hipMemcpyAsync(b(USTATE), wk + (size_t)k * bytes, bytes, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipGraphLaunch(gadj, s));
+        HIPCHK(hipGraphLaunch(gadj[scheme], s));
       }
     }
     HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
@@ -572,6 +615,11 @@ int sem_rhs(sem_ctx c, const void* u, void* f) { return apply_entry(c, OP_RHS, u
 int sem_jac_vec(sem_ctx c, const void* u, const void* v, void* jv) { return apply_entry(c, OP_JAC, u, v, jv); }
 int sem_jact_vec(sem_ctx c, const void* u, const void* w, void* jtw) { return apply_entry(c, OP_JACT, u, w, jtw); }
 
+static int check_scheme(int32_t scheme) {
+  if (scheme != SEM_RK4 && scheme != SEM_RK3) return fail(SEM_ERR_ARG, "unknown time-integration scheme %d", scheme);
+  return SEM_OK;
+}
+
 static int check_steps(double dt, int32_t nsteps, int32_t K, bool need_k) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SEM_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(SEM_ERR_ARG, "nsteps %d < 0", nsteps);
@@ -586,15 +634,16 @@ int sem_set_check_finite(sem_ctx c, int32_t on) {
   return SEM_OK;
 }
 
-int sem_rk4_forward(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt) {
+int sem_rk_forward(sem_ctx c, int32_t scheme, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
   if (!u) return fail(SEM_ERR_ARG, "null u");
-  int rc = check_steps(dt, nsteps, K, ckpt != nullptr);
+  int rc = check_scheme(scheme);
   if (rc) return rc;
+  if ((rc = check_steps(dt, nsteps, K, ckpt != nullptr))) return rc;
   if (ckpt && ckpt == u) return fail(SEM_ERR_ARG, "ckpt aliases u");
-  if ((rc = c->integ.prepare())) return rc;
+  if ((rc = c->integ.prepare(scheme))) return rc;
   if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
-  if ((rc = c->integ.forward(u, nsteps, K, ckpt, c->stream))) return rc;
+  if ((rc = c->integ.forward(scheme, u, nsteps, K, ckpt, c->stream))) return rc;
   if (c->check_finite) {
     HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
     const int64_t n = c->integ.n;
@@ -620,15 +669,25 @@ int sem_workspace_bytes(sem_ctx c, int32_t K, int64_t* bytes) {
   return SEM_OK;
 }
 
-int sem_rk4_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam, void* work) {
+int sem_rk4_forward(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt) {
+  return sem_rk_forward(c, SEM_RK4, u, dt, nsteps, K, ckpt);
+}
+
+int sem_rk_adjoint(sem_ctx c, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam,
+                   void* work) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
   if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
-  int rc = check_steps(dt, nsteps, K, true);
+  int rc = check_scheme(scheme);
   if (rc) return rc;
+  if ((rc = check_steps(dt, nsteps, K, true))) return rc;
   if (lam == ckpt || lam == work || work == ckpt) return fail(SEM_ERR_ARG, "aliased buffers");
-  if ((rc = c->integ.prepare())) return rc;
+  if ((rc = c->integ.prepare(scheme))) return rc;
   if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
-  return c->integ.adjoint(ckpt, nsteps, K, lam, work, c->stream);
+  return c->integ.adjoint(scheme, ckpt, nsteps, K, lam, work, c->stream);
+}
+
+int sem_rk4_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam, void* work) {
+  return sem_rk_adjoint(c, SEM_RK4, ckpt, dt, nsteps, K, lam, work);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -728,22 +787,35 @@ int sem_batch_workspace_bytes(sem_batch b, int32_t K, int64_t* bytes) {
   return SEM_OK;
 }
 
-int sem_batch_rk4_forward(sem_batch b, void* u, int32_t nsteps, int32_t K, void* ckpt) {
+int sem_batch_rk_forward(sem_batch b, int32_t scheme, void* u, int32_t nsteps, int32_t K, void* ckpt) {
   if (!b) return fail(SEM_ERR_ARG, "null batch");
   if (!u) return fail(SEM_ERR_ARG, "null u");
-  int rc = check_steps(1.0, nsteps, K, ckpt != nullptr);
+  int rc = check_scheme(scheme);
   if (rc) return rc;
-  if ((rc = b->integ.prepare())) return rc;
-  return b->integ.forward(u, nsteps, K, ckpt, b->stream);
+  if ((rc = check_steps(1.0, nsteps, K, ckpt != nullptr))) return rc;
+  if (ckpt && ckpt == u) return fail(SEM_ERR_ARG, "ckpt aliases u");
+  if ((rc = b->integ.prepare(scheme))) return rc;
+  return b->integ.forward(scheme, u, nsteps, K, ckpt, b->stream);
+}
+
+int sem_batch_rk4_forward(sem_batch b, void* u, int32_t nsteps, int32_t K, void* ckpt) {
+  return sem_batch_rk_forward(b, SEM_RK4, u, nsteps, K, ckpt);
+}
+
+int sem_batch_rk_adjoint(sem_batch b, int32_t scheme, const void* ckpt, int32_t nsteps, int32_t K, void* lam,
+                         void* work) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if ((rc = check_steps(1.0, nsteps, K, true))) return rc;
+  if (lam == ckpt || lam == work || work == ckpt) return fail(SEM_ERR_ARG, "aliased buffers");
+  if ((rc = b->integ.prepare(scheme))) return rc;
+  return b->integ.adjoint(scheme, ckpt, nsteps, K, lam, work, b->stream);
 }
 
 int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t K, void* lam, void* work) {
-  if (!b) return fail(SEM_ERR_ARG, "null batch");
-  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
-  int rc = check_steps(1.0, nsteps, K, true);
-  if (rc) return rc;
-  if ((rc = b->integ.prepare())) return rc;
-  return b->integ.adjoint(ckpt, nsteps, K, lam, work, b->stream);
+  return sem_batch_rk_adjoint(b, SEM_RK4, ckpt, nsteps, K, lam, work);
 }
 
 int sem_batch_configure(sem_batch b, int32_t persistent, int32_t param) {
@@ -808,13 +880,13 @@ int sem_batch_autotune(sem_batch b, double* best_ms) {
   int rc = SEM_OK;
   for (auto [pm, prm] : cand) {
     if ((rc = sem_batch_configure(b, pm, prm))) break;
-    if ((rc = b->integ.prepare())) break;
+    if ((rc = b->integ.prepare(SEM_RK4))) break;
     // time the captured RK4 step on a zero state (values do not change the work)
     hipError_t he = hipMemsetAsync(b->integ.b(Integrator::STATE), 0, b->integ.n * b->integ.ts, s);
-    for (int w = 0; w < 2 && he == hipSuccess; ++w) he = hipGraphLaunch(b->integ.gstep, s);
+    for (int w = 0; w < 2 && he == hipSuccess; ++w) he = hipGraphLaunch(b->integ.gstep[SEM_RK4], s);
     if (he == hipSuccess) he = hipEventRecord(e0, s);
     const int R = 5;
-    for (int r = 0; r < R && he == hipSuccess; ++r) he = hipGraphLaunch(b->integ.gstep, s);
+    for (int r = 0; r < R && he == hipSuccess; ++r) he = hipGraphLaunch(b->integ.gstep[SEM_RK4], s);
     if (he == hipSuccess) he = hipEventRecord(e1, s);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
     float ms = 0;

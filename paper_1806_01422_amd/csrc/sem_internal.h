@@ -43,8 +43,8 @@ struct Coef {
 };
 
 // Epilogue of the summation (DSS) kernels: s is the assembled operator value at a node;
-//   o1 = a1 * x1 + b1 * s   (x1 may be NULL: then o1 = b1 * s)
-//   o2 = a2 * x2 + b2 * s   (optional; o2 may equal x2)
+//   o1 = a1 * x1 + c1 * x2 + b1 * s   (a NULL x contributes 0)
+//   o2 = a2 * x2 + c2 * x1 + b2 * s   (optional; o2 may equal x2; o1 never aliases x1 or x2)
 struct Epi {
   void* o1;
   const void* x1;
@@ -52,6 +52,7 @@ struct Epi {
   void* o2;
   const void* x2;
   Coef a2, b2;
+  Coef c1, c2;  // cross terms: o1 += c1 x2, o2 += c2 x1 (RK-3 stage combinations)
 };
 
 enum Op { OP_RHS = 0, OP_JAC = 1, OP_JACT = 2 };

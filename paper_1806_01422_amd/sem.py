@@ -16,6 +16,16 @@ LIB_PATH = os.path.join(_HERE, "libsem.so")
 SEM_F64, SEM_F32 = 0, 1
 
 
+# time-integration schemes (sem_scheme): classical RK4 and the three-stage RK-3 (Kutta's tableau)
+SCHEMES = {"rk4": 0, "rk3": 1}
+
+
+def _scheme(name):
+    if name not in SCHEMES:
+        raise SemError(f"unknown scheme {name!r}; expected one of {sorted(SCHEMES)}")
+    return SCHEMES[name]
+
+
 class SemError(RuntimeError):
     pass
 
@@ -50,6 +60,10 @@ _SIGS = {
     "sem_batch_jact_vec": [_vp, _vp, _vp, _vp],
     "sem_batch_rk4_forward": [_vp, _vp, _i32, _i32, _vp],
     "sem_batch_rk4_adjoint": [_vp, _vp, _i32, _i32, _vp, _vp],
+    "sem_rk_forward": [_vp, _i32, _vp, _f64, _i32, _i32, _vp],
+    "sem_rk_adjoint": [_vp, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
+    "sem_batch_rk_forward": [_vp, _i32, _vp, _i32, _i32, _vp],
+    "sem_batch_rk_adjoint": [_vp, _i32, _vp, _i32, _i32, _vp, _vp],
     "sem_batch_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
     "sem_batch_configure": [_vp, _i32, _i32],
     "sem_batch_autotune": [_vp, ctypes.POINTER(_f64)],
@@ -194,20 +208,45 @@ class Context:
         _call(lib().sem_workspace_bytes(self._h, int(ckpt_every), ctypes.byref(b)))
         return b.value
 
-    def rk4_adjoint(self, ckpt, dt, nsteps, ckpt_every, lamT, work=None):
-        """lambda_0 = dPhi/du_0 from lambda_N = dPhi/du(T) (discrete RK4 adjoint)."""
+    def _adjoint_args(self, ckpt, nsteps, ckpt_every, lamT, work):
         self._chk(lamT, "lamT")
         if not ckpt.is_contiguous() or ckpt.dtype != self.dtype:
             raise SemError("ckpt must be a contiguous tensor of the context dtype")
         if ckpt.numel() != (nsteps // ckpt_every) * self.batch * self.ndof:
             raise SemError("ckpt has the wrong size")
-        lam = lamT.clone()
         if work is None:
             nbytes = self.workspace_bytes(ckpt_every)
             work = torch.empty(nbytes // (8 if self.dtype == torch.float64 else 4), dtype=self.dtype, device="cuda")
+        return lamT.clone(), work
+
+    def rk4_adjoint(self, ckpt, dt, nsteps, ckpt_every, lamT, work=None):
+        """lambda_0 = dPhi/du_0 from lambda_N = dPhi/du(T) (discrete RK4 adjoint)."""
+        lam, work = self._adjoint_args(ckpt, nsteps, ckpt_every, lamT, work)
         self._bind()
         _call(lib().sem_rk4_adjoint(self._h, _ptr(ckpt), float(dt), int(nsteps), int(ckpt_every), _ptr(lam),
                                     _ptr(work)))
+        return lam
+
+    def rk_forward(self, u0, dt, nsteps, ckpt_every=0, scheme="rk4", inplace=False):
+        """rk4_forward for any scheme ("rk4", "rk3")."""
+        self._chk(u0, "u0")
+        code = _scheme(scheme)
+        u = u0 if inplace else u0.clone()
+        ck = None
+        if ckpt_every:
+            ck = torch.empty((nsteps // ckpt_every,) + self.shape, dtype=self.dtype, device="cuda")
+        self._bind()
+        _call(lib().sem_rk_forward(self._h, code, _ptr(u), float(dt), int(nsteps), int(ckpt_every),
+                                   _ptr(ck) if ck is not None else None))
+        return u, ck
+
+    def rk_adjoint(self, ckpt, dt, nsteps, ckpt_every, lamT, scheme="rk4", work=None):
+        """rk4_adjoint for any scheme ("rk4", "rk3")."""
+        code = _scheme(scheme)
+        lam, work = self._adjoint_args(ckpt, nsteps, ckpt_every, lamT, work)
+        self._bind()
+        _call(lib().sem_rk_adjoint(self._h, code, _ptr(ckpt), float(dt), int(nsteps), int(ckpt_every), _ptr(lam),
+                                   _ptr(work)))
         return lam
 
 
@@ -227,25 +266,26 @@ class SEMRhs(torch.autograd.Function):
 
 
 class SEMTrajectory(torch.autograd.Function):
-    """u(T) = RK4^nsteps(u_0) with backward by the discrete RK4 adjoint (Sec. 4.1) from uniform
-    checkpoints every ckpt_every steps, recomputed segment by segment (Sec. 5.3)."""
+    """u(T) = Phi_dt^nsteps(u_0) for an explicit RK scheme ("rk4" or "rk3"), with backward by the
+    discrete adjoint of that scheme (Sec. 4.1) from uniform checkpoints every ckpt_every steps,
+    recomputed segment by segment (Sec. 5.3)."""
 
     @staticmethod
-    def forward(ctx, u0, sem, dt, nsteps, ckpt_every):
-        uT, ck = sem.rk4_forward(u0.contiguous(), dt, nsteps, ckpt_every)
-        ctx.sem, ctx.dt, ctx.nsteps, ctx.K = sem, dt, nsteps, ckpt_every
+    def forward(ctx, u0, sem, dt, nsteps, ckpt_every, scheme="rk4"):
+        uT, ck = sem.rk_forward(u0.contiguous(), dt, nsteps, ckpt_every, scheme=scheme)
+        ctx.sem, ctx.dt, ctx.nsteps, ctx.K, ctx.scheme = sem, dt, nsteps, ckpt_every, scheme
         ctx.save_for_backward(ck)
         return uT
 
     @staticmethod
     def backward(ctx, g):
         (ck,) = ctx.saved_tensors
-        lam0 = ctx.sem.rk4_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous())
-        return lam0, None, None, None, None
+        lam0 = ctx.sem.rk_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous(), scheme=ctx.scheme)
+        return lam0, None, None, None, None, None
 
 
-def trajectory(u0, sem, dt, nsteps, ckpt_every):
-    return SEMTrajectory.apply(u0, sem, dt, nsteps, ckpt_every)
+def trajectory(u0, sem, dt, nsteps, ckpt_every, scheme="rk4"):
+    return SEMTrajectory.apply(u0, sem, dt, nsteps, ckpt_every, scheme)
 
 
 class Batch:
@@ -317,14 +357,38 @@ class Batch:
                                           _ptr(ck) if ck is not None else None))
         return u, ck
 
-    def rk4_adjoint(self, ckpt, nsteps, ckpt_every, lamT, work=None):
-        self._chk(lamT, "lamT")
-        lam = lamT.clone()
+    def _work(self, ckpt_every, work):
         if work is None:
             b = _i64()
             _call(lib().sem_batch_workspace_bytes(self._h, int(ckpt_every), ctypes.byref(b)))
             work = torch.empty(b.value // (8 if self.dtype == torch.float64 else 4), dtype=self.dtype, device="cuda")
+        return work
+
+    def rk4_adjoint(self, ckpt, nsteps, ckpt_every, lamT, work=None):
+        self._chk(lamT, "lamT")
+        lam = lamT.clone()
+        work = self._work(ckpt_every, work)
         _call(lib().sem_batch_rk4_adjoint(self._h, _ptr(ckpt), int(nsteps), int(ckpt_every), _ptr(lam), _ptr(work)))
+        return lam
+
+    def rk_forward(self, u0, nsteps, ckpt_every=0, scheme="rk4"):
+        self._chk(u0, "u0")
+        code = _scheme(scheme)
+        u = u0.clone()
+        ck = None
+        if ckpt_every:
+            ck = torch.empty((nsteps // ckpt_every, self.total), dtype=self.dtype, device="cuda")
+        _call(lib().sem_batch_rk_forward(self._h, code, _ptr(u), int(nsteps), int(ckpt_every),
+                                         _ptr(ck) if ck is not None else None))
+        return u, ck
+
+    def rk_adjoint(self, ckpt, nsteps, ckpt_every, lamT, scheme="rk4", work=None):
+        self._chk(lamT, "lamT")
+        code = _scheme(scheme)
+        lam = lamT.clone()
+        work = self._work(ckpt_every, work)
+        _call(lib().sem_batch_rk_adjoint(self._h, code, _ptr(ckpt), int(nsteps), int(ckpt_every), _ptr(lam),
+                                         _ptr(work)))
         return lam
 
     def configure(self, persistent, param=0):

@@ -288,6 +288,82 @@ def test_batch_trajectory_gradient(P):
 
 
 # ------------------------------------------------------------------------------------------------
+# RK-3 (Kutta's tableau) forward and discrete adjoint: fused stage kernels vs the oracle's general
+# explicit Runge-Kutta
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,N,E,batch", [(1, 8, [16], 1), (2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1),
+                                           (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2)])
+def test_rk3_forward_adjoint(P, dim, N, E, batch):
+    note(f"RK-3 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    u, _, w = fields(m, 19)
+    dt, n, K = (2e-3 if dim > 1 else 2e-4), 20, 5  # the 1-D N=8 mesh on [0, 1] needs the smaller step
+    uT_ref, ck_ref = m.erk_forward("rk3", u, dt, n, K)
+    assert np.isfinite(uT_ref).all()
+    uT, ck = c.rk_forward(gpu(u), dt, n, K, scheme="rk3")
+    assert rel(uT, uT_ref) < TOL_TRAJ
+    assert rel(ck, ck_ref) < TOL_TRAJ
+    lam_ref = m.erk_adjoint("rk3", ck_ref, dt, n, K, w)
+    lam = c.rk_adjoint(ck, dt, n, K, gpu(w), scheme="rk3")
+    assert rel(lam, lam_ref) < TOL_TRAJ
+    # the RK4 entry points and the generic ones with scheme "rk4" are the same integrator
+    a, _ = c.rk4_forward(gpu(u), dt, n)
+    b, _ = c.rk_forward(gpu(u), dt, n, scheme="rk4")
+    assert torch.equal(a, b)
+
+
+def test_rk3_trajectory_gradient_fd(P):
+    note("C1 mesh: RK-3 trajectory, autograd gradient vs oracle and finite differences")
+    m, u0, target = c1_inputs()
+    c = P.Context(1, wl.C1.N, wl.C1.E, wl.C1.L, wl.C1.nu)
+    dt, n, K = wl.C1_DT, wl.C1_STEPS, 10
+    x = gpu(u0).requires_grad_(True)
+    yT = P.trajectory(x, c, dt, n, K, scheme="rk3")
+    loss = 0.5 * ((yT - gpu(target)) ** 2).sum()
+    loss.backward()
+    uT_ref, ck_ref = m.erk_forward("rk3", u0, dt, n, K)
+    phi_ref, lamT = m.misfit(uT_ref, target)
+    g_ref = m.erk_adjoint("rk3", ck_ref, dt, n, K, lamT)
+    assert abs(loss.item() - phi_ref[0]) < 1e-12 * abs(phi_ref[0])
+    assert rel(x.grad, g_ref) < TOL_TRAJ
+
+    def Phi(uu):
+        yy, _ = c.rk_forward(gpu(uu), dt, n, scheme="rk3")
+        return 0.5 * ((yy - gpu(target)) ** 2).sum().item()
+    g = x.grad.cpu().numpy()
+    for s in range(8):
+        d = wl.normal_field(m.shape, 300 + s)
+        eps = 1e-4 * np.linalg.norm(u0) / np.linalg.norm(d)
+        fd = (8 * (Phi(u0 + eps * d) - Phi(u0 - eps * d)) - (Phi(u0 + 2 * eps * d) - Phi(u0 - 2 * eps * d))) / (
+            12 * eps)
+        ad = float(np.vdot(g, d))
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (s, fd, ad)
+
+
+def test_batch_rk3(P):
+    note("batched uneven set (8 problems): RK-3 forward + adjoint vs per-problem oracle")
+    specs, probs = batch_problems(8)
+    B = P.Batch(specs)
+    u, lam = B.empty(), B.empty()
+    for i, (s, p) in enumerate(zip(specs, probs)):
+        m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
+        xs = [m.coords(k) for k in range(2)]
+        B.view(u, i).copy_(gpu(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]))
+        B.view(lam, i).copy_(gpu(wl.normal_field(m.shape, p.target_seed)))
+    n, K = 8, 4
+    uT, ck = B.rk_forward(u, n, K, scheme="rk3")
+    lam0 = B.rk_adjoint(ck, n, K, lam, scheme="rk3")
+    for i, s in enumerate(specs):
+        if s["elems"][0] > 16:
+            continue  # keep the oracle side short
+        m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
+        ref, ckr = m.erk_forward("rk3", B.view(u, i).cpu().numpy(), s["dt"], n, K)
+        assert rel(B.view(uT, i), ref) < TOL_TRAJ, i
+        lr = m.erk_adjoint("rk3", ckr, s["dt"], n, K, B.view(lam, i).cpu().numpy())
+        assert rel(B.view(lam0, i), lr) < TOL_TRAJ, i
+
+
+# ------------------------------------------------------------------------------------------------
 # Error handling at the boundary
 # ------------------------------------------------------------------------------------------------
 def test_errors(P):
@@ -306,6 +382,10 @@ def test_errors(P):
         c.rk4_forward(u, -1.0, 10, 0)
     with pytest.raises(P.SemError):
         c.rhs(torch.zeros(5, dtype=torch.float64, device="cuda"))
+    with pytest.raises(P.SemError):
+        c.rk_forward(u, 1e-3, 10, scheme="rk2")  # unknown scheme (binding)
+    with pytest.raises(P.SemError):
+        P.sem._call(P.lib().sem_rk_forward(c._h, 7, P.sem._ptr(u), 1e-3, 10, 0, None))  # unknown scheme (ABI)
 
 
 def test_nonfinite_detection(P):
