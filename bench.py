@@ -50,6 +50,7 @@ def log(msg):
 def event_time_ms(fn, reps):
     """Average milliseconds per call of fn over reps calls, HIP events on the current stream."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()  # warm-up: first-call set-up (module load, graph capture) stays out of the timing
     torch.cuda.synchronize()
     s.record()
     for _ in range(reps):
@@ -160,6 +161,32 @@ def gradient_c5(P, nsteps=wl.C5_STEPS, K=50):
             "autotuned_rk4_step_ms": round(step_ms, 4)}
 
 
+def rk_adjoint_ratio(P, nsteps=10):
+    """Forward and discrete-adjoint time per step of RK-3 and RK4 on the 3-D 32^3 N=7 FP64 field:
+    checkpoints every step (the adjoint recomputes only stage states) and every 5 steps (segment
+    recompute as well)."""
+    cfg = wl.C3
+    ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
+    U, _, W = c3_inputs(ctx, torch.float64)
+    dt = 1e-4
+    out = {"workload": f"3-D 32^3 N=7 FP64, {nsteps} steps, dt={dt}"}
+    for scheme in ("rk3", "rk4"):
+        res = {}
+        for K in (1, 5):
+            uT, ck = ctx.rk_forward(U, dt, nsteps, K, scheme=scheme)  # warm-up (graph capture)
+            work = torch.empty(ctx.workspace_bytes(K) // 8, dtype=torch.float64, device="cuda")
+            ctx.rk_adjoint(ck, dt, nsteps, K, W, scheme=scheme, work=work)
+            t_f = event_time_ms(lambda: ctx.rk_forward(U, dt, nsteps, K, scheme=scheme), 3) / nsteps
+            t_a = event_time_ms(lambda: ctx.rk_adjoint(ck, dt, nsteps, K, W, scheme=scheme, work=work), 3) / nsteps
+            res[f"K{K}"] = {"forward_ms_per_step": round(t_f, 4), "adjoint_ms_per_step": round(t_a, 4),
+                            "adjoint_over_forward": round(t_a / t_f, 3)}
+            del ck, work
+        out[scheme] = res
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +292,8 @@ def main():
         log("c4 done")
         out["c5_batched"] = gradient_c5(P)
         log("c5 done")
+        out["rk_adjoint"] = rk_adjoint_ratio(P)
+        log("rk adjoint ratio done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
         log("cpu baseline done")

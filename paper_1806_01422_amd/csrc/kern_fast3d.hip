@@ -438,6 +438,9 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
           for (int q = 0; q < 8; ++q) tQ[i * 512 + tix(q, l0, l1)] = qv[q] + P[q];
           R7[i] = qv[7] + P[7];
         });
+    // epilogue operands of this layer: issued before the barrier so that their latency overlaps it
+    T E1[3][7], E2[3][7];
+    load_epi(ez, E1, E2, ez == 0 ? 1 : 0, 7);
     // ---- x-direction summation inside the workgroup: wavefront w's face a = 7 is wavefront
     // w + 1's face a = 0 (double-buffered by step parity: one barrier per step)
     const int par = ez & 1;
@@ -467,11 +470,7 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
       for (int i = 0; i < 3; ++i) first0[i] = Zv[i][0];
     }
     // ---- outputs (plane c = 0 of layer 0 waits for the periodic wrap)
-    {
-      T E1[3][7], E2[3][7];
-      load_epi(ez, E1, E2, ez == 0 ? 1 : 0, 7);
-      emit(ez, Zv, ez == 0 ? 1 : 0, 7, E1, E2);
-    }
+    emit(ez, Zv, ez == 0 ? 1 : 0, 7, E1, E2);
   }
   // periodic wrap along z: the carried plane of the last layer is plane c = 0 of layer 0
   {
@@ -534,11 +533,17 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   const T* x1 = epi.x1 ? static_cast<const T*>(epi.x1) + o : nullptr;
   T* o2 = epi.o2 ? static_cast<T*>(epi.o2) + o : nullptr;
   const T* x2 = epi.x2 ? static_cast<const T*>(epi.x2) + o : nullptr;
+  // all operands first: a store may alias a later operand, so the loads must not wait behind it
+  T v1[4], v2[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const T v1 = x1 ? x1[q] : (T)0, v2 = x2 ? x2[q] : (T)0;
-    T r1 = b1 * s[q] + a1 * v1 + c1 * v2;
-    if (o2) o2[q] = b2 * s[q] + a2 * v2 + c2 * v1;
+    v1[q] = x1 ? x1[q] : (T)0;
+    v2[q] = x2 ? x2[q] : (T)0;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    T r1 = b1 * s[q] + a1 * v1[q] + c1 * v2[q];
+    if (o2) o2[q] = b2 * s[q] + a2 * v2[q] + c2 * v1[q];
     o1[q] = r1;
   }
 }
