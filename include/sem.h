@@ -114,6 +114,25 @@ int sem_rk4_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, in
 int sem_rk_forward(sem_ctx ctx, int32_t scheme, void* u, double dt, int32_t nsteps, int32_t ckpt_every, void* ckpt);
 int sem_rk_adjoint(sem_ctx ctx, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every,
                    void* lam, void* work);
+/* Binomial (revolve) checkpointing (Sec. 5.3: recompute the forward trajectory from a few stored
+   states; the paper's runs use PETSc's revolve).  With `snaps` state slots the adjoint advances
+   the least number of forward steps any schedule with that many slots needs.
+   - sem_revolve_plan (host only): the schedule as `nactions` (kind, arg) pairs in `actions`
+     (host int64 array of 2 * capacity entries; NULL to query nactions).  Kinds: 0 RESTORE slot
+     (current state <- slot), 1 ADVANCE k steps, 2 STORE slot (slot <- current state), 3 ADJOINT i
+     (adjoint of step i from the current state u_i).  Slot 0 holds u_0.  advances (may be NULL)
+     receives the number of forward steps in the schedule.  SEM_ERR_ARG if capacity is too small.
+   - sem_rk_forward_revolve: like sem_rk_forward (u in: u_0, out: u(T)) and stores the
+     schedule's first snapshots into ckpt[snaps][batch][ndof].
+   - sem_rk_adjoint_revolve: lam in: lambda_N, out: lambda_0 from that ckpt (read only); work
+     holds sem_revolve_workspace_bytes(ctx, snaps) bytes.  Bitwise equal to sem_rk_adjoint with the
+     same scheme, dt and nsteps. */
+int sem_revolve_plan(int32_t nsteps, int32_t snaps, int64_t* nactions, int64_t* actions, int64_t capacity,
+                     int64_t* advances);
+int sem_rk_forward_revolve(sem_ctx ctx, int32_t scheme, void* u, double dt, int32_t nsteps, int32_t snaps, void* ckpt);
+int sem_rk_adjoint_revolve(sem_ctx ctx, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t snaps,
+                           void* lam, void* work);
+int sem_revolve_workspace_bytes(sem_ctx ctx, int32_t snaps, int64_t* bytes);
 /* Bytes of caller work buffer needed by sem_rk4_adjoint / sem_rk_adjoint for a given ckpt_every. */
 int sem_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, int64_t* bytes);
 /* Enable (1) or disable (0, default) the non-finite check at the end of sem_rk4_forward (one

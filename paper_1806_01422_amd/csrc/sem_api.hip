@@ -515,6 +515,82 @@ struct Integrator {
     HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
     return SEM_OK;
   }
+
+  // Binomial checkpointing.  The forward sweep stores the schedule's first snapshots (the states
+  // its actions store before the first adjoint step) into ckpt slots; the adjoint sweep copies
+  // them to work and runs the rest of the schedule there.
+  static size_t first_adjoint(const std::vector<RevolveAct>& acts) {
+    size_t k = 0;
+    while (k < acts.size() && acts[k].kind != REV_ADJOINT) ++k;
+    while (k > 0 && acts[k].kind != REV_RESTORE) --k;  // its restore starts the adjoint sweep
+    return k;
+  }
+
+  int forward_revolve(int scheme, void* u, int32_t nsteps, const std::vector<RevolveAct>& acts, void* ckpt,
+                      hipStream_t s) {
+    const size_t bytes = n * ts;
+    std::vector<int64_t> slot_at(nsteps, -1);  // snapshot slot taking the state before step k
+    int64_t p = 0;
+    std::vector<int64_t> slot_pos(1, 0);  // step index held by each slot
+    for (size_t k = 0; k < first_adjoint(acts); ++k) {
+      const RevolveAct& a = acts[k];
+      if (a.kind == REV_RESTORE) {
+        if (a.arg >= (int64_t)slot_pos.size()) return fail(SEM_ERR_ARG, "schedule restores an empty slot");
+        p = slot_pos[a.arg];
+      }
+      if (a.kind == REV_ADVANCE) p += a.arg;
+      if (a.kind == REV_STORE) {
+        if ((int64_t)slot_pos.size() <= a.arg) slot_pos.resize(a.arg + 1, 0);
+        slot_pos[a.arg] = p;
+        slot_at[p] = a.arg;
+      }
+    }
+    slot_at[0] = 0;
+    HIPCHK(hipMemcpyAsync(b(STATE), u, bytes, hipMemcpyDeviceToDevice, s));
+    for (int32_t k = 0; k < nsteps; ++k) {
+      if (slot_at[k] >= 0)
+        HIPCHK(hipMemcpyAsync(static_cast<char*>(ckpt) + (size_t)slot_at[k] * bytes, b(STATE), bytes,
+                              hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipGraphLaunch(gstep[scheme], s));
+    }
+    HIPCHK(hipMemcpyAsync(u, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
+    return SEM_OK;
+  }
+
+  int adjoint_revolve(int scheme, const void* ckpt, int32_t snaps, const std::vector<RevolveAct>& acts, void* lam,
+                      void* work, hipStream_t s) {
+    const size_t bytes = n * ts;
+    char* wk = static_cast<char*>(work);
+    HIPCHK(hipMemcpyAsync(wk, ckpt, (size_t)snaps * bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
+    for (size_t k = first_adjoint(acts); k < acts.size(); ++k) {
+      const RevolveAct& a = acts[k];
+      switch (a.kind) {
+        case REV_RESTORE: {
+          // a restore followed directly by an adjoint step goes straight to the step's input
+          const bool direct = k + 1 < acts.size() && acts[k + 1].kind == REV_ADJOINT;
+          HIPCHK(hipMemcpyAsync(b(direct ? USTATE : STATE), wk + (size_t)a.arg * bytes, bytes,
+                                hipMemcpyDeviceToDevice, s));
+          if (direct) {
+            HIPCHK(hipGraphLaunch(gadj[scheme], s));
+            ++k;
+          }
+          break;
+        }
+        case REV_ADVANCE:
+          for (int64_t i = 0; i < a.arg; ++i) HIPCHK(hipGraphLaunch(gstep[scheme], s));
+          break;
+        case REV_STORE:
+          HIPCHK(hipMemcpyAsync(wk + (size_t)a.arg * bytes, b(STATE), bytes, hipMemcpyDeviceToDevice, s));
+          break;
+        default:  // REV_ADJOINT after an advance
+          HIPCHK(hipMemcpyAsync(b(USTATE), b(STATE), bytes, hipMemcpyDeviceToDevice, s));
+          HIPCHK(hipGraphLaunch(gadj[scheme], s));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
+    return SEM_OK;
+  }
 };
 
 }  // namespace
@@ -688,6 +764,63 @@ int sem_rk_adjoint(sem_ctx c, int32_t scheme, const void* ckpt, double dt, int32
 
 int sem_rk4_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam, void* work) {
   return sem_rk_adjoint(c, SEM_RK4, ckpt, dt, nsteps, K, lam, work);
+}
+
+int sem_revolve_plan(int32_t nsteps, int32_t snaps, int64_t* nactions, int64_t* actions, int64_t capacity,
+                     int64_t* advances) {
+  if (!nactions) return fail(SEM_ERR_ARG, "null nactions");
+  if (nsteps < 1 || snaps < 1) return fail(SEM_ERR_ARG, "need nsteps >= 1 and snaps >= 1 (got %d, %d)", nsteps, snaps);
+  std::vector<RevolveAct> acts;
+  const int64_t adv = revolve_plan(nsteps, snaps, acts);
+  *nactions = (int64_t)acts.size();
+  if (advances) *advances = adv;
+  if (!actions) return SEM_OK;
+  if (capacity < (int64_t)acts.size())
+    return fail(SEM_ERR_ARG, "action buffer holds %lld actions, the schedule has %lld", (long long)capacity,
+                (long long)acts.size());
+  for (size_t k = 0; k < acts.size(); ++k) {
+    actions[2 * k] = acts[k].kind;
+    actions[2 * k + 1] = acts[k].arg;
+  }
+  return SEM_OK;
+}
+
+int sem_revolve_workspace_bytes(sem_ctx c, int32_t snaps, int64_t* bytes) {
+  if (!c || !bytes) return fail(SEM_ERR_ARG, "null argument");
+  if (snaps < 1) return fail(SEM_ERR_ARG, "snaps %d < 1", snaps);
+  *bytes = (int64_t)snaps * c->integ.n * (int64_t)c->os.ts;
+  return SEM_OK;
+}
+
+int sem_rk_forward_revolve(sem_ctx c, int32_t scheme, void* u, double dt, int32_t nsteps, int32_t snaps, void* ckpt) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!u || !ckpt) return fail(SEM_ERR_ARG, "null pointer");
+  if (ckpt == u) return fail(SEM_ERR_ARG, "ckpt aliases u");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if ((rc = check_steps(dt, nsteps, 1, false))) return rc;
+  if (nsteps < 1 || snaps < 1) return fail(SEM_ERR_ARG, "need nsteps >= 1 and snaps >= 1 (got %d, %d)", nsteps, snaps);
+  std::vector<RevolveAct> acts;
+  revolve_plan(nsteps, snaps, acts);
+  if ((rc = c->integ.prepare(scheme))) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  return c->integ.forward_revolve(scheme, u, nsteps, acts, ckpt, c->stream);
+}
+
+int sem_rk_adjoint_revolve(sem_ctx c, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t snaps,
+                           void* lam, void* work) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  if (lam == ckpt || lam == work || work == ckpt) return fail(SEM_ERR_ARG, "aliased buffers");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if ((rc = check_steps(dt, nsteps, 1, false))) return rc;
+  if (nsteps < 1 || snaps < 1) return fail(SEM_ERR_ARG, "need nsteps >= 1 and snaps >= 1 (got %d, %d)", nsteps, snaps);
+  std::vector<RevolveAct> acts;
+  revolve_plan(nsteps, snaps, acts);
+  if ((rc = c->integ.prepare(scheme))) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  return c->integ.adjoint_revolve(scheme, ckpt, snaps, acts, lam, work, c->stream);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 #include <string>
 
 #include "sem.h"
@@ -99,6 +100,18 @@ bool fast3d_supported(const ProbDev& hp);
 int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch
 size_t fast3d_table_bytes();
 void fast3d_fill_tables(int N, void* host);  // fills fast3d_table_bytes() bytes
+
+// Binomial checkpointing schedule (revolve.cpp).  Actions, in order: RESTORE slot (current state
+// <- snapshot slot), ADVANCE k (k forward steps), STORE slot (snapshot slot <- current state),
+// ADJOINT i (adjoint of step i on the current state, which is u_i).  Slot 0 holds u_0.
+enum { REV_RESTORE = 0, REV_ADVANCE = 1, REV_STORE = 2, REV_ADJOINT = 3 };
+struct RevolveAct {
+  int kind;
+  int64_t arg;
+};
+// Fills acts for nsteps steps and snaps snapshot slots; returns the number of forward steps the
+// schedule advances (-1 for invalid sizes).
+int64_t revolve_plan(int64_t nsteps, int64_t snaps, std::vector<RevolveAct>& acts);
 hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
                          const Epi& epi, Coef in_scale, const void* dtables, int dtype, hipStream_t s);
 

@@ -60,6 +60,10 @@ _SIGS = {
     "sem_batch_jact_vec": [_vp, _vp, _vp, _vp],
     "sem_batch_rk4_forward": [_vp, _vp, _i32, _i32, _vp],
     "sem_batch_rk4_adjoint": [_vp, _vp, _i32, _i32, _vp, _vp],
+    "sem_revolve_plan": [_i32, _i32, _vp, _vp, _i64, _vp],
+    "sem_rk_forward_revolve": [_vp, _i32, _vp, _f64, _i32, _i32, _vp],
+    "sem_rk_adjoint_revolve": [_vp, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
+    "sem_revolve_workspace_bytes": [_vp, _i32, _vp],
     "sem_rk_forward": [_vp, _i32, _vp, _f64, _i32, _i32, _vp],
     "sem_rk_adjoint": [_vp, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
     "sem_batch_rk_forward": [_vp, _i32, _vp, _i32, _i32, _vp],
@@ -250,6 +254,44 @@ class Context:
         return lam
 
 
+    def rk_forward_revolve(self, u0, dt, nsteps, snaps, scheme="rk4"):
+        """(u(T), snapshots [snaps][batch][C][...]) for binomial checkpointing with snaps slots."""
+        self._chk(u0, "u0")
+        code = _scheme(scheme)
+        u = u0.clone()
+        ck = torch.empty((int(snaps),) + self.shape, dtype=self.dtype, device="cuda")
+        self._bind()
+        _call(lib().sem_rk_forward_revolve(self._h, code, _ptr(u), float(dt), int(nsteps), int(snaps), _ptr(ck)))
+        return u, ck
+
+    def rk_adjoint_revolve(self, ckpt, dt, nsteps, snaps, lamT, scheme="rk4", work=None):
+        """lambda_0 from lambda_N by the binomial schedule, from rk_forward_revolve's snapshots."""
+        self._chk(lamT, "lamT")
+        code = _scheme(scheme)
+        if not ckpt.is_contiguous() or ckpt.dtype != self.dtype or ckpt.numel() != snaps * self.batch * self.ndof:
+            raise SemError("ckpt must be the contiguous [snaps][batch][...] tensor of rk_forward_revolve")
+        if work is None:
+            b = _i64()
+            _call(lib().sem_revolve_workspace_bytes(self._h, int(snaps), ctypes.byref(b)))
+            work = torch.empty(b.value // (8 if self.dtype == torch.float64 else 4), dtype=self.dtype, device="cuda")
+        lam = lamT.clone()
+        self._bind()
+        _call(lib().sem_rk_adjoint_revolve(self._h, code, _ptr(ckpt), float(dt), int(nsteps), int(snaps), _ptr(lam),
+                                           _ptr(work)))
+        return lam
+
+
+def revolve_plan(nsteps, snaps):
+    """The binomial checkpointing schedule: (list of (kind, arg) with kinds "restore", "advance",
+    "store", "adjoint"; number of forward steps it advances).  Host only."""
+    n, adv = _i64(), _i64()
+    _call(lib().sem_revolve_plan(int(nsteps), int(snaps), ctypes.byref(n), None, 0, ctypes.byref(adv)))
+    buf = (_i64 * (2 * n.value))()
+    _call(lib().sem_revolve_plan(int(nsteps), int(snaps), ctypes.byref(n), buf, n.value, ctypes.byref(adv)))
+    kinds = ("restore", "advance", "store", "adjoint")
+    return [(kinds[buf[2 * k]], int(buf[2 * k + 1])) for k in range(n.value)], adv.value
+
+
 class SEMRhs(torch.autograd.Function):
     """f = F(u) with backward u_bar = J(u)^T f_bar (Sec. 3.3, eq. jactransvec)."""
 
@@ -286,6 +328,27 @@ class SEMTrajectory(torch.autograd.Function):
 
 def trajectory(u0, sem, dt, nsteps, ckpt_every, scheme="rk4"):
     return SEMTrajectory.apply(u0, sem, dt, nsteps, ckpt_every, scheme)
+
+
+class SEMTrajectoryRevolve(torch.autograd.Function):
+    """SEMTrajectory with binomial (revolve) checkpointing in `snaps` state slots."""
+
+    @staticmethod
+    def forward(ctx, u0, sem, dt, nsteps, snaps, scheme="rk4"):
+        uT, ck = sem.rk_forward_revolve(u0.contiguous(), dt, nsteps, snaps, scheme=scheme)
+        ctx.sem, ctx.dt, ctx.nsteps, ctx.snaps, ctx.scheme = sem, dt, nsteps, snaps, scheme
+        ctx.save_for_backward(ck)
+        return uT
+
+    @staticmethod
+    def backward(ctx, g):
+        (ck,) = ctx.saved_tensors
+        lam0 = ctx.sem.rk_adjoint_revolve(ck, ctx.dt, ctx.nsteps, ctx.snaps, g.contiguous(), scheme=ctx.scheme)
+        return lam0, None, None, None, None, None
+
+
+def trajectory_revolve(u0, sem, dt, nsteps, snaps, scheme="rk4"):
+    return SEMTrajectoryRevolve.apply(u0, sem, dt, nsteps, snaps, scheme)
 
 
 class Batch:

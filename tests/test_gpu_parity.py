@@ -364,6 +364,43 @@ def test_batch_rk3(P):
 
 
 # ------------------------------------------------------------------------------------------------
+# Binomial (revolve) checkpointing: same step graphs as uniform checkpointing, so bitwise equal
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme", ["rk4", "rk3"])
+@pytest.mark.parametrize("dim,N,E,batch,snaps", [(2, 5, [4, 3], 2, 3), (3, 7, [4, 2, 3], 1, 4), (1, 6, [9], 1, 1)])
+def test_revolve_matches_uniform(P, scheme, dim, N, E, batch, snaps):
+    note(f"revolve {scheme} dim={dim} N={N} E={E} batch={batch} snaps={snaps}")
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    u, _, w = fields(m, 23)
+    dt, n = (2e-3 if dim > 1 else 2e-4), 17
+    uT_u, ck_u = c.rk_forward(gpu(u), dt, n, 1, scheme=scheme)
+    lam_u = c.rk_adjoint(ck_u, dt, n, 1, gpu(w), scheme=scheme)
+    uT_r, ck_r = c.rk_forward_revolve(gpu(u), dt, n, snaps, scheme=scheme)
+    assert torch.equal(uT_r, uT_u)
+    lam_r = c.rk_adjoint_revolve(ck_r, dt, n, snaps, gpu(w), scheme=scheme)
+    assert torch.equal(lam_r, lam_u)
+    ck_copy = ck_r.clone()
+    assert torch.equal(c.rk_adjoint_revolve(ck_r, dt, n, snaps, gpu(w), scheme=scheme), lam_u)  # repeatable
+    assert torch.equal(ck_r, ck_copy)  # snapshots are read only
+    ref, ckr = m.erk_forward(scheme, u, dt, n, 1)
+    assert rel(uT_r, ref) < TOL_TRAJ
+    assert rel(lam_r, m.erk_adjoint(scheme, ckr, dt, n, 1, w)) < TOL_TRAJ
+
+
+def test_revolve_trajectory_autograd(P):
+    note("revolve trajectory gradient equals the uniform one")
+    m, u0, target = c1_inputs()
+    c = P.Context(1, wl.C1.N, wl.C1.E, wl.C1.L, wl.C1.nu)
+    dt, n = wl.C1_DT, wl.C1_STEPS
+    grads = []
+    for f in (lambda x: P.trajectory(x, c, dt, n, 10), lambda x: P.trajectory_revolve(x, c, dt, n, 4)):
+        x = gpu(u0).requires_grad_(True)
+        (0.5 * ((f(x) - gpu(target)) ** 2).sum()).backward()
+        grads.append(x.grad)
+    assert torch.equal(grads[0], grads[1])
+
+
+# ------------------------------------------------------------------------------------------------
 # Error handling at the boundary
 # ------------------------------------------------------------------------------------------------
 def test_errors(P):
