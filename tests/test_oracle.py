@@ -532,3 +532,91 @@ def test_rk3_checkpointing_is_bitwise_store_all():
         lams.append(m.erk_adjoint("rk3", ck, dt, n, K, lamT))
     np.testing.assert_array_equal(lams[0], lams[1])
     np.testing.assert_array_equal(lams[0], lams[2])
+
+
+# ------------------------------------------------------------------------------------------------
+# Crank-Nicolson (the paper's implicit scheme, Sec. 6.3) with Newton, and its discrete adjoint
+# ------------------------------------------------------------------------------------------------
+from oracle import cn as ocn  # noqa: E402
+
+
+def test_cn_step_solves_its_equation():
+    m = mesh(2, 4, [3, 2], nu=0.02)
+    u = wl.fourier_field([m.coords(0), m.coords(1)], [1, 1], 3, 31)[None]
+    dt = 5e-3
+    v = ocn.cn_step(m, u, dt)
+    R = v - u - 0.5 * dt * (m.rhs(u) + m.rhs(v))
+    assert np.abs(R).max() < 1e-14 * np.abs(v).max()
+
+
+def test_cn_second_order_in_dt():
+    nu, a, T = 0.1, 1.25, 0.5
+    m = oracle.Mesh(1, 8, [4], [4.0], nu)
+    u0 = cole_hopf(m.coords(0), 0.0, nu, a)[None, None]
+    ref, _ = m.rk4_forward(u0, 2.5e-4, 2000)
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        uT, _ = ocn.cn_forward(m, u0, dt, int(round(T / dt)))
+        errs.append(rel(uT, ref))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.8 < r < 2.2 for r in rates), (errs, rates)
+
+
+def test_cn_frozen_speed_advection_diffusion():
+    nu, T, dt = 1e-3, 0.05, 5e-4
+    amp = wl.rng(4).uniform(0.9, 1.0, 5)
+    m = mesh(1, 12, [6], nu=nu)
+    X = grids(m)
+
+    def exact(t):
+        s = 0.0
+        for j, aj in enumerate(amp[:3], start=1):
+            s = s + aj * np.sin(2 * np.pi * j * (X[0] - 0.1 * t)) * np.exp(-nu * 4 * np.pi ** 2 * j * j * t)
+        return s[None, None]
+
+    ubar = np.full((1, 1) + X[0].shape, 0.1)
+    _, vT = ocn.cn_tlm(m, ubar, exact(0.0), dt, int(round(T / dt)))
+    assert rel(vT, exact(T)) < 1e-7
+
+
+def test_cn_adjoint_gradient_vs_finite_differences():
+    m, u0, target = c1_inputs()
+    dt, n, K = wl.C1_DT, 20, 5
+    uT, ck = ocn.cn_forward(m, u0, dt, n, K)
+    _, lamT = m.misfit(uT, target)
+    g = ocn.cn_adjoint(m, ck, dt, n, K, lamT)
+
+    def Phi(u):
+        return m.misfit(ocn.cn_forward(m, u, dt, n)[0], target)[0][0]
+
+    for s in range(4):
+        d = wl.normal_field(m.shape, 300 + s)
+        eps = 1e-4 * np.linalg.norm(u0) / np.linalg.norm(d)
+        fd = (8 * (Phi(u0 + eps * d) - Phi(u0 - eps * d)) - (Phi(u0 + 2 * eps * d) - Phi(u0 - 2 * eps * d))) \
+            / (12 * eps)
+        ad = np.vdot(g, d)
+        assert abs(fd - ad) <= 1e-8 * abs(ad), (s, fd, ad)
+
+
+def test_cn_tangent_linear_adjoint_duality():
+    m = mesh(2, 4, [3, 2], nu=0.01)
+    u0 = wl.fourier_field([m.coords(0), m.coords(1)], [1, 1], 3, 9)[None]
+    du0, lamN = rand(m, 10), rand(m, 11)
+    dt, n, K = 2e-3, 6, 3
+    _, duN = ocn.cn_tlm(m, u0, du0, dt, n)
+    _, ck = ocn.cn_forward(m, u0, dt, n, K)
+    lam0 = ocn.cn_adjoint(m, ck, dt, n, K, lamN)
+    a, b = np.vdot(lam0, du0), np.vdot(lamN, duN)
+    assert abs(a - b) < 1e-12 * abs(b)
+
+
+def test_cn_checkpointing_is_bitwise_store_all():
+    m, u0, target = c1_inputs()
+    dt, n = wl.C1_DT, 10
+    lams = []
+    for K in (1, 5, 10):
+        uT, ck = ocn.cn_forward(m, u0, dt, n, K)
+        _, lamT = m.misfit(uT, target)
+        lams.append(ocn.cn_adjoint(m, ck, dt, n, K, lamT))
+    np.testing.assert_array_equal(lams[0], lams[1])
+    np.testing.assert_array_equal(lams[0], lams[2])
