@@ -40,7 +40,8 @@ typedef enum {
   SEM_ERR_UNSUPPORTED = -2, /* order N or dimension outside the compiled range */
   SEM_ERR_HIP = -3,         /* a HIP runtime call failed (message carries the HIP error) */
   SEM_ERR_NOMEM = -4,       /* device allocation failed */
-  SEM_ERR_NONFINITE = -5    /* a trajectory produced a non-finite value (when checking is on) */
+  SEM_ERR_NONFINITE = -5,   /* a trajectory produced a non-finite value (when checking is on) */
+  SEM_ERR_NOCONV = -6       /* a Newton or Krylov iteration did not reach its tolerance */
 } sem_status;
 
 typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
@@ -133,6 +134,39 @@ int sem_rk_forward_revolve(sem_ctx ctx, int32_t scheme, void* u, double dt, int3
 int sem_rk_adjoint_revolve(sem_ctx ctx, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t snaps,
                            void* lam, void* work);
 int sem_revolve_workspace_bytes(sem_ctx ctx, int32_t snaps, int64_t* bytes);
+/* Crank-Nicolson, the paper's implicit scheme (Sec. 6.3), with a Newton-Krylov solve per step
+   (Sec. 2: Newton-type nonlinear solves with Krylov linear solves and matrix-free Jacobians).
+   Each step solves R(v) = v - u - dt/2 (F(u) + F(v)) = 0 by Newton's method from the predictor
+   u + dt F(u); the corrections solve (I - dt/2 J(v)) d = R(v) by restarted GMRES with matrix-free
+   J v products.  The discrete adjoint of the exact step map (Sec. 4.1, eq. adjtime) needs linear
+   solves only: (I - dt/2 J(u_{n+1}))^T mu = lambda_{n+1} by GMRES with J^T products, then
+   lambda_n = mu + dt/2 J(u_n)^T mu.  Each adjoint segment recomputes its K + 1 states from the
+   checkpoint.  Both calls synchronise the stream (the iterations read norms on the host) and are
+   not capturable.  A batch (desc.batch > 1) is solved as one block-diagonal system.
+   opts may be NULL (defaults); stats (may be NULL) receives the iteration counts. */
+typedef struct {
+  double newton_rtol;    /* stop when ||R||_2 <= newton_rtol ||u + dt/2 F(u)||_2; 0: 1e-13 (FP64), 1e-6 (FP32) */
+  int32_t newton_maxit;  /* Newton iterations per step; 0: 25 */
+  double gmres_rtol;     /* relative residual of each linear solve; 0: 1e-11 (FP64), 1e-5 (FP32) */
+  int32_t gmres_restart; /* Krylov basis size between restarts, 1..39; 0: 30 */
+  int32_t gmres_maxit;   /* GMRES iterations per linear solve; 0: 300 */
+} sem_nk_opts;
+typedef struct {
+  int64_t newton_iters;    /* Newton iterations, all steps */
+  int64_t linear_solves;   /* GMRES solves */
+  int64_t gmres_iters;     /* GMRES iterations (J v or J^T w products), all solves */
+  double max_rel_residual; /* largest final relative residual of any Newton or GMRES solve */
+} sem_nk_stats;
+/* Bytes of the caller work buffer of sem_cn_forward and sem_cn_adjoint (the adjoint's is larger:
+   (K + 1) + (restart + 2) states; the forward needs restart + 2). */
+int sem_cn_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, const sem_nk_opts* opts, int64_t* bytes);
+/* u in: u_0, out: u(T); checkpoints as in sem_rk4_forward (ckpt may be NULL).  SEM_ERR_NOCONV when
+   Newton or GMRES does not converge within its iteration limit. */
+int sem_cn_forward(sem_ctx ctx, void* u, double dt, int32_t nsteps, int32_t ckpt_every, void* ckpt,
+                   const sem_nk_opts* opts, void* work, sem_nk_stats* stats);
+/* lam in: lambda_N, out: lambda_0, from sem_cn_forward's checkpoints. */
+int sem_cn_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every, void* lam,
+                   const sem_nk_opts* opts, void* work, sem_nk_stats* stats);
 /* Bytes of caller work buffer needed by sem_rk4_adjoint / sem_rk_adjoint for a given ckpt_every. */
 int sem_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, int64_t* bytes);
 /* Enable (1) or disable (0, default) the non-finite check at the end of sem_rk4_forward (one

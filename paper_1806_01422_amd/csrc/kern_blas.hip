@@ -1,0 +1,122 @@
+// Vector kernels for the Newton-Krylov solvers: dot products of one vector with several others
+// (deterministic two-stage reduction in FP64) and combinations y = a y + sum_j c_j x_j with the
+// coefficients read from device memory, so a Gram-Schmidt step needs no host round trip between
+// its projection and its update.
+#include "sem_internal.h"
+
+namespace sem {
+namespace {
+
+constexpr int BT = 256;       // threads per block
+constexpr int MAXV = 40;      // most vectors in one multi-dot or combination
+constexpr int DOT_BLOCKS = 512;
+
+// partial[b][j] = sum over this block's strided range of x_j[i] * w[i]
+template <typename T>
+__global__ __launch_bounds__(BT) void multidot_partial(const T* __restrict__ X, int64_t ldx, int nv,
+                                                       const T* __restrict__ w, int64_t n,
+                                                       double* __restrict__ partial) {
+  __shared__ double red[BT / 64][MAXV];
+  double acc[MAXV];
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) acc[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+    const double wi = (double)w[i];
+#pragma unroll
+    for (int j = 0; j < MAXV; ++j)
+      if (j < nv) acc[j] += (double)X[j * ldx + i] * wi;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < MAXV; ++j) {
+    if (j >= nv) break;
+    double v = acc[j];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double s = 0.0;
+    for (int k = 0; k < BT / 64; ++k) s += red[k][threadIdx.x];
+    partial[(int64_t)blockIdx.x * MAXV + threadIdx.x] = s;
+  }
+}
+
+// out[j] = sum over blocks of partial[b][j] (fixed order)
+__global__ void multidot_final(const double* __restrict__ partial, int nblocks, int nv, double* __restrict__ out) {
+  const int j = threadIdx.x;
+  if (j >= nv) return;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * MAXV + j];
+  out[j] = s;
+}
+
+// y = alpha * y + sum_j sign * coef[j] * x_j   (coef in device memory)
+template <typename T>
+__global__ __launch_bounds__(BT) void combine(T* __restrict__ y, double alpha, const T* __restrict__ X, int64_t ldx,
+                                              int nv, const double* __restrict__ coef, double sign, int64_t n) {
+  __shared__ double c[MAXV];
+  if (threadIdx.x < nv) c[threadIdx.x] = sign * coef[threadIdx.x];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+    double s = alpha == 0.0 ? 0.0 : alpha * (double)y[i];
+    for (int j = 0; j < nv; ++j) s += c[j] * (double)X[j * ldx + i];
+    y[i] = (T)s;
+  }
+}
+
+// z = a x + b y
+template <typename T>
+__global__ __launch_bounds__(BT) void axpby_kernel(T* __restrict__ z, double a, const T* __restrict__ x, double b,
+                                                   const T* __restrict__ y, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT)
+    z[i] = (T)(a * (double)x[i] + (y ? b * (double)y[i] : 0.0));
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t b = (n + BT - 1) / BT;
+  return (unsigned)(b < 2048 ? (b < 1 ? 1 : b) : 2048);
+}
+
+}  // namespace
+
+int blas_max_vectors() { return MAXV; }
+size_t blas_partial_bytes() { return sizeof(double) * DOT_BLOCKS * MAXV; }
+
+hipError_t blas_multidot(int dtype, const void* X, int64_t ldx, int nv, const void* w, int64_t n, double* partial,
+                         double* out, hipStream_t s) {
+  const int64_t need = (n + BT - 1) / BT;
+  const int nb = (int)(need < DOT_BLOCKS ? (need < 1 ? 1 : need) : DOT_BLOCKS);
+  if (dtype == SEM_F64)
+    hipLaunchKernelGGL(multidot_partial<double>, dim3(nb), dim3(BT), 0, s, static_cast<const double*>(X), ldx, nv,
+                       static_cast<const double*>(w), n, partial);
+  else
+    hipLaunchKernelGGL(multidot_partial<float>, dim3(nb), dim3(BT), 0, s, static_cast<const float*>(X), ldx, nv,
+                       static_cast<const float*>(w), n, partial);
+  hipLaunchKernelGGL(multidot_final, dim3(1), dim3(64), 0, s, partial, nb, nv, out);
+  return hipGetLastError();
+}
+
+hipError_t blas_combine(int dtype, void* y, double alpha, const void* X, int64_t ldx, int nv, const double* coef,
+                        double sign, int64_t n, hipStream_t s) {
+  if (dtype == SEM_F64)
+    hipLaunchKernelGGL(combine<double>, dim3(grid_for(n)), dim3(BT), 0, s, static_cast<double*>(y), alpha,
+                       static_cast<const double*>(X), ldx, nv, coef, sign, n);
+  else
+    hipLaunchKernelGGL(combine<float>, dim3(grid_for(n)), dim3(BT), 0, s, static_cast<float*>(y), alpha,
+                       static_cast<const float*>(X), ldx, nv, coef, sign, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_axpby(int dtype, void* z, double a, const void* x, double b, const void* y, int64_t n,
+                      hipStream_t s) {
+  if (dtype == SEM_F64)
+    hipLaunchKernelGGL(axpby_kernel<double>, dim3(grid_for(n)), dim3(BT), 0, s, static_cast<double*>(z), a,
+                       static_cast<const double*>(x), b, static_cast<const double*>(y), n);
+  else
+    hipLaunchKernelGGL(axpby_kernel<float>, dim3(grid_for(n)), dim3(BT), 0, s, static_cast<float*>(z), a,
+                       static_cast<const float*>(x), b, static_cast<const float*>(y), n);
+  return hipGetLastError();
+}
+
+}  // namespace sem

@@ -439,13 +439,18 @@ struct Integrator {
     return os->apply(OP_JACT, b(USTATE), b(T1), one, ep, s);
   }
 
-  int prepare(int scheme) {
-    if (ready[scheme]) return SEM_OK;
+  int alloc_buffers() {
     for (int i = 0; i < NBUF; ++i) {
       if (buf[i].p) continue;
       int rc = buf[i].alloc(n * ts);
       if (rc) return rc;
     }
+    return SEM_OK;
+  }
+
+  int prepare(int scheme) {
+    if (ready[scheme]) return SEM_OK;
+    if (int rc = alloc_buffers()) return rc;
     if (!cap) HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -593,6 +598,208 @@ struct Integrator {
   }
 };
 
+// Crank-Nicolson with Newton-Krylov solves on the integrator's state buffers plus a caller work
+// buffer (GMRES basis, and the recomputed states of an adjoint segment).
+struct Implicit {
+  Integrator* in = nullptr;
+  double* partial = nullptr;  // blas_partial_bytes()
+  double* dvec = nullptr;     // 2 * blas_max_vectors() doubles: dot results and combination weights
+  hipStream_t s = nullptr;
+  double newton_rtol = 0, gmres_rtol = 0;
+  int newton_maxit = 0, restart = 0, gmres_maxit = 0;
+  sem_nk_stats st{};
+
+  int dtype() const { return in->os->dtype; }
+  int64_t n() const { return in->n; }
+  size_t bytes() const { return (size_t)in->n * in->ts; }
+
+  int configure(const sem_nk_opts* o) {
+    const bool f64 = dtype() == SEM_F64;
+    newton_rtol = (o && o->newton_rtol > 0) ? o->newton_rtol : (f64 ? 1e-13 : 1e-6);
+    gmres_rtol = (o && o->gmres_rtol > 0) ? o->gmres_rtol : (f64 ? 1e-11 : 1e-5);
+    newton_maxit = (o && o->newton_maxit > 0) ? o->newton_maxit : 25;
+    restart = (o && o->gmres_restart > 0) ? o->gmres_restart : 30;
+    gmres_maxit = (o && o->gmres_maxit > 0) ? o->gmres_maxit : 300;
+    if (restart > blas_max_vectors() - 1)
+      return fail(SEM_ERR_ARG, "gmres_restart %d exceeds %d", restart, blas_max_vectors() - 1);
+    st = sem_nk_stats{};
+    return SEM_OK;
+  }
+
+  // host copies of <X_j, w>, j < nv (the device copy stays in dvec for a following combination)
+  int dots(const void* X, int nv, const void* w, double* h) {
+    HIPCHK(blas_multidot(dtype(), X, in->n, nv, w, in->n, partial, dvec, s));
+    HIPCHK(hipMemcpyAsync(h, dvec, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SEM_OK;
+  }
+  int norm(const void* w, double* r) {
+    double h = 0;
+    if (int rc = dots(w, 1, w, &h)) return rc;
+    *r = std::sqrt(h > 0 ? h : 0.0);
+    return SEM_OK;
+  }
+
+  // out = p + cdt * dt * op(at) p  (op: J or J^T at the state `at`)
+  hipError_t matvec(int op, const void* at, double cdt, const void* p, void* out) {
+    const Coef one{1, 0}, zero{0, 0};
+    Epi ep{out, p, one, {0, cdt}, nullptr, nullptr, zero, zero};
+    return in->os->apply(op, at, p, one, ep, s);
+  }
+
+  // Restarted GMRES for (I + cdt dt op(at)) x = b from x = 0; basis: restart + 1 vectors, then one
+  // more vector of scratch.  Classical Gram-Schmidt, applied twice.
+  int gmres(int op, const void* at, double cdt, const void* b, void* x, char* basis) {
+    const size_t B = bytes();
+    const int m = restart;
+    auto V = [&](int j) { return basis + (size_t)j * B; };
+    char* tmp = V(m + 1);
+    double bnorm = 0;
+    if (int rc = norm(b, &bnorm)) return rc;
+    HIPCHK(blas_axpby(dtype(), x, 0.0, b, 0.0, nullptr, in->n, s));  // x = 0
+    ++st.linear_solves;
+    if (!(bnorm > 0)) return std::isfinite(bnorm) ? SEM_OK : fail(SEM_ERR_NONFINITE, "non-finite Krylov right-hand side");
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 1), h2(m + 1);
+    int total = 0;
+    double res = bnorm;
+    bool first = true;
+    while (true) {
+      // r = b - A x  (x = 0 on the first cycle)
+      if (first) {
+        HIPCHK(blas_axpby(dtype(), V(0), 1.0 / bnorm, b, 0.0, nullptr, in->n, s));
+        res = bnorm;
+      } else {
+        HIPCHK(matvec(op, at, cdt, x, tmp));
+        HIPCHK(blas_axpby(dtype(), tmp, 1.0, b, -1.0, tmp, in->n, s));
+        if (int rc = norm(tmp, &res)) return rc;
+        if (!(res > 0)) break;
+        HIPCHK(blas_axpby(dtype(), V(0), 1.0 / res, tmp, 0.0, nullptr, in->n, s));
+      }
+      first = false;
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = res;
+      int k = 0;
+      for (; k < m && total < gmres_maxit; ++k, ++total) {
+        HIPCHK(matvec(op, at, cdt, V(k), V(k + 1)));
+        if (int rc = dots(V(0), k + 1, V(k + 1), h.data())) return rc;
+        HIPCHK(blas_combine(dtype(), V(k + 1), 1.0, V(0), in->n, k + 1, dvec, -1.0, in->n, s));
+        if (int rc = dots(V(0), k + 1, V(k + 1), h2.data())) return rc;
+        HIPCHK(blas_combine(dtype(), V(k + 1), 1.0, V(0), in->n, k + 1, dvec, -1.0, in->n, s));
+        double hn = 0;
+        if (int rc = norm(V(k + 1), &hn)) return rc;
+        for (int i = 0; i <= k; ++i) H[i * m + k] = h[i] + h2[i];
+        H[(k + 1) * m + k] = hn;
+        if (hn > 0) HIPCHK(blas_axpby(dtype(), V(k + 1), 1.0 / hn, V(k + 1), 0.0, nullptr, in->n, s));
+        for (int i = 0; i < k; ++i) {  // earlier rotations
+          const double a = H[i * m + k], c = H[(i + 1) * m + k];
+          H[i * m + k] = cs[i] * a + sn[i] * c;
+          H[(i + 1) * m + k] = -sn[i] * a + cs[i] * c;
+        }
+        const double a = H[k * m + k], c = H[(k + 1) * m + k], r = std::hypot(a, c);
+        cs[k] = r > 0 ? a / r : 1.0;
+        sn[k] = r > 0 ? c / r : 0.0;
+        H[k * m + k] = r;
+        H[(k + 1) * m + k] = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        if (!std::isfinite(g[k + 1])) return fail(SEM_ERR_NONFINITE, "non-finite GMRES residual");
+        if (std::fabs(g[k + 1]) <= gmres_rtol * bnorm || hn == 0.0) {
+          ++k, ++total;
+          break;
+        }
+      }
+      // x += V y with H y = g (upper triangular k x k)
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int j = i + 1; j < k; ++j) t -= H[i * m + j] * y[j];
+        y[i] = t / H[i * m + i];
+      }
+      HIPCHK(hipMemcpyAsync(dvec, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+      HIPCHK(blas_combine(dtype(), x, 1.0, V(0), in->n, k, dvec, 1.0, in->n, s));
+      res = std::fabs(g[k]);
+      if (res <= gmres_rtol * bnorm) break;
+      if (total >= gmres_maxit)
+        return fail(SEM_ERR_NOCONV, "GMRES stopped at relative residual %.3g after %d iterations", res / bnorm, total);
+    }
+    st.gmres_iters += total;
+    st.max_rel_residual = std::max(st.max_rel_residual, res / bnorm);
+    return SEM_OK;
+  }
+
+  // one Crank-Nicolson step on u (device state, overwritten), Newton from the predictor u + dt F(u)
+  int cn_step(void* u, char* basis) {
+    using I = Integrator;
+    const Coef one{1, 0}, zero{0, 0};
+    void* Bv = in->b(I::S1);  // u + dt/2 F(u)
+    void* v = in->b(I::S2);   // Newton iterate
+    void* R = in->b(I::ACC);  // residual
+    void* d = in->b(I::T1);   // correction
+    Epi ep{Bv, u, one, {0, 0.5}, v, u, one, {0, 1.0}};
+    HIPCHK(in->os->apply(OP_RHS, u, nullptr, one, ep, s));
+    double bn = 0;
+    if (int rc = norm(Bv, &bn)) return rc;
+    const double scale = bn > 0 ? bn : 1.0;
+    double rn = 0;
+    for (int it = 0;; ++it) {
+      ep = Epi{R, v, one, {0, -0.5}, nullptr, Bv, zero, zero, {-1, 0}, zero};  // R = v - B - dt/2 F(v)
+      HIPCHK(in->os->apply(OP_RHS, v, nullptr, one, ep, s));
+      if (int rc = norm(R, &rn)) return rc;
+      if (!std::isfinite(rn)) return fail(SEM_ERR_NONFINITE, "non-finite Newton residual (dt too large?)");
+      if (rn <= newton_rtol * scale) break;
+      if (it >= newton_maxit)
+        return fail(SEM_ERR_NOCONV, "Newton stopped at relative residual %.3g after %d iterations", rn / scale, it);
+      ++st.newton_iters;
+      if (int rc = gmres(OP_JAC, v, -0.5, R, d, basis)) return rc;
+      HIPCHK(blas_axpby(dtype(), v, 1.0, v, -1.0, d, in->n, s));
+    }
+    st.max_rel_residual = std::max(st.max_rel_residual, rn / scale);
+    HIPCHK(hipMemcpyAsync(u, v, bytes(), hipMemcpyDeviceToDevice, s));
+    return SEM_OK;
+  }
+
+  int forward(void* u, int32_t nsteps, int32_t K, void* ckpt, char* work) {
+    using I = Integrator;
+    void* x = in->b(I::STATE);
+    HIPCHK(hipMemcpyAsync(x, u, bytes(), hipMemcpyDeviceToDevice, s));
+    for (int32_t k = 0; k < nsteps; ++k) {
+      if (ckpt && k % K == 0)
+        HIPCHK(hipMemcpyAsync(static_cast<char*>(ckpt) + (size_t)(k / K) * bytes(), x, bytes(),
+                              hipMemcpyDeviceToDevice, s));
+      if (int rc = cn_step(x, work)) return rc;
+    }
+    HIPCHK(hipMemcpyAsync(u, x, bytes(), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SEM_OK;
+  }
+
+  // work: K + 1 states of the segment, then the GMRES basis
+  int adjoint(const void* ckpt, int32_t nsteps, int32_t K, void* lam, char* work) {
+    using I = Integrator;
+    const Coef one{1, 0}, zero{0, 0};
+    const size_t B = bytes();
+    char* basis = work + (size_t)(K + 1) * B;
+    void* L = in->b(I::LAMB);
+    void* mu = in->b(I::T2);
+    HIPCHK(hipMemcpyAsync(L, lam, B, hipMemcpyDeviceToDevice, s));
+    for (int sg = nsteps / K - 1; sg >= 0; --sg) {
+      HIPCHK(hipMemcpyAsync(work, static_cast<const char*>(ckpt) + (size_t)sg * B, B, hipMemcpyDeviceToDevice, s));
+      for (int k = 1; k <= K; ++k) {
+        HIPCHK(hipMemcpyAsync(work + (size_t)k * B, work + (size_t)(k - 1) * B, B, hipMemcpyDeviceToDevice, s));
+        if (int rc = cn_step(work + (size_t)k * B, basis)) return rc;
+      }
+      for (int k = K - 1; k >= 0; --k) {
+        // (I - dt/2 J(u_{k+1}))^T mu = lam;  lam = mu + dt/2 J(u_k)^T mu
+        if (int rc = gmres(OP_JACT, work + (size_t)(k + 1) * B, -0.5, L, mu, basis)) return rc;
+        Epi ep{L, mu, one, {0, 0.5}, nullptr, nullptr, zero, zero};
+        HIPCHK(in->os->apply(OP_JACT, work + (size_t)k * B, mu, one, ep, s));
+      }
+    }
+    HIPCHK(hipMemcpyAsync(lam, L, B, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SEM_OK;
+  }
+};
+
 }  // namespace
 
 struct sem_ctx_s {
@@ -603,6 +810,7 @@ struct sem_ctx_s {
   int64_t ndof = 0, nodes = 0;
   bool check_finite = false;
   DevBuf flag;
+  DevBuf nk;  // Newton-Krylov reductions: partial sums, then dot results / combination weights
 };
 
 struct sem_batch_s {
@@ -636,7 +844,7 @@ int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out) {
   c->integ.os = &c->os;
   c->integ.n = c->ndof * desc->batch;
   c->integ.ts = c->os.ts;
-  if ((rc = c->flag.alloc(sizeof(int)))) {
+  if ((rc = c->flag.alloc(sizeof(int))) || (rc = c->nk.alloc(blas_partial_bytes() + 2 * sizeof(double) * blas_max_vectors()))) {
     delete c;
     return rc;
   }
@@ -764,6 +972,53 @@ int sem_rk_adjoint(sem_ctx c, int32_t scheme, const void* ckpt, double dt, int32
 
 int sem_rk4_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam, void* work) {
   return sem_rk_adjoint(c, SEM_RK4, ckpt, dt, nsteps, K, lam, work);
+}
+
+static int cn_setup(sem_ctx c, const sem_nk_opts* opts, Implicit& im) {
+  im.in = &c->integ;
+  im.partial = static_cast<double*>(c->nk.p);
+  im.dvec = reinterpret_cast<double*>(static_cast<char*>(c->nk.p) + blas_partial_bytes());
+  im.s = c->stream;
+  if (int rc = im.configure(opts)) return rc;
+  return c->integ.alloc_buffers();
+}
+
+int sem_cn_workspace_bytes(sem_ctx c, int32_t K, const sem_nk_opts* opts, int64_t* bytes) {
+  if (!c || !bytes) return fail(SEM_ERR_ARG, "null argument");
+  if (K < 1) return fail(SEM_ERR_ARG, "ckpt_every %d < 1", K);
+  const int restart = (opts && opts->gmres_restart > 0) ? opts->gmres_restart : 30;
+  *bytes = (int64_t)(K + 1 + restart + 2) * c->integ.n * (int64_t)c->os.ts;
+  return SEM_OK;
+}
+
+int sem_cn_forward(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt, const sem_nk_opts* opts,
+                   void* work, sem_nk_stats* stats) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!u || !work) return fail(SEM_ERR_ARG, "null pointer");
+  if ((ckpt && (ckpt == u || ckpt == work)) || work == u) return fail(SEM_ERR_ARG, "aliased buffers");
+  int rc = check_steps(dt, nsteps, K, ckpt != nullptr);
+  if (rc) return rc;
+  Implicit im;
+  if ((rc = cn_setup(c, opts, im))) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  rc = im.forward(u, nsteps, K, ckpt, static_cast<char*>(work));
+  if (stats) *stats = im.st;
+  return rc;
+}
+
+int sem_cn_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam,
+                   const sem_nk_opts* opts, void* work, sem_nk_stats* stats) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  if (lam == ckpt || lam == work || work == ckpt) return fail(SEM_ERR_ARG, "aliased buffers");
+  int rc = check_steps(dt, nsteps, K, true);
+  if (rc) return rc;
+  Implicit im;
+  if ((rc = cn_setup(c, opts, im))) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  rc = im.adjoint(ckpt, nsteps, K, lam, static_cast<char*>(work));
+  if (stats) *stats = im.st;
+  return rc;
 }
 
 int sem_revolve_plan(int32_t nsteps, int32_t snaps, int64_t* nactions, int64_t* actions, int64_t capacity,

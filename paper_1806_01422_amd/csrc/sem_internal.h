@@ -101,6 +101,17 @@ int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch
 size_t fast3d_table_bytes();
 void fast3d_fill_tables(int N, void* host);  // fills fast3d_table_bytes() bytes
 
+// Vector kernels (kern_blas.hip): out[j] = <X_j, w> for nv <= blas_max_vectors() vectors X_j at
+// stride ldx (FP64 accumulation, fixed order; partial holds blas_partial_bytes()), and
+// y = alpha y + sign * sum_j coef[j] X_j with coef in device memory, and z = a x + b y (y may be NULL).
+int blas_max_vectors();
+size_t blas_partial_bytes();
+hipError_t blas_multidot(int dtype, const void* X, int64_t ldx, int nv, const void* w, int64_t n, double* partial,
+                         double* out, hipStream_t s);
+hipError_t blas_combine(int dtype, void* y, double alpha, const void* X, int64_t ldx, int nv, const double* coef,
+                        double sign, int64_t n, hipStream_t s);
+hipError_t blas_axpby(int dtype, void* z, double a, const void* x, double b, const void* y, int64_t n, hipStream_t s);
+
 // Binomial checkpointing schedule (revolve.cpp).  Actions, in order: RESTORE slot (current state
 // <- snapshot slot), ADVANCE k (k forward steps), STORE slot (snapshot slot <- current state),
 // ADJOINT i (adjoint of step i on the current state, which is u_i).  Slot 0 holds u_0.

@@ -26,6 +26,21 @@ def _scheme(name):
     return SCHEMES[name]
 
 
+class NkOpts(ctypes.Structure):
+    """sem_nk_opts: Newton-Krylov settings of the Crank-Nicolson calls (zeros select defaults)."""
+    _fields_ = [("newton_rtol", ctypes.c_double), ("newton_maxit", ctypes.c_int32), ("gmres_rtol", ctypes.c_double),
+                ("gmres_restart", ctypes.c_int32), ("gmres_maxit", ctypes.c_int32)]
+
+
+class NkStats(ctypes.Structure):
+    """sem_nk_stats: iteration counts of a Crank-Nicolson call."""
+    _fields_ = [("newton_iters", ctypes.c_int64), ("linear_solves", ctypes.c_int64), ("gmres_iters", ctypes.c_int64),
+                ("max_rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class SemError(RuntimeError):
     pass
 
@@ -64,6 +79,9 @@ _SIGS = {
     "sem_rk_forward_revolve": [_vp, _i32, _vp, _f64, _i32, _i32, _vp],
     "sem_rk_adjoint_revolve": [_vp, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
     "sem_revolve_workspace_bytes": [_vp, _i32, _vp],
+    "sem_cn_workspace_bytes": [_vp, _i32, _vp, _vp],
+    "sem_cn_forward": [_vp, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
+    "sem_cn_adjoint": [_vp, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
     "sem_rk_forward": [_vp, _i32, _vp, _f64, _i32, _i32, _vp],
     "sem_rk_adjoint": [_vp, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
     "sem_batch_rk_forward": [_vp, _i32, _vp, _i32, _i32, _vp],
@@ -254,6 +272,46 @@ class Context:
         return lam
 
 
+    def _nk(self, opts):
+        o = NkOpts()
+        for k, v in (opts or {}).items():
+            setattr(o, k, v)
+        return o
+
+    def cn_workspace_bytes(self, ckpt_every, opts=None):
+        b = _i64()
+        _call(lib().sem_cn_workspace_bytes(self._h, int(ckpt_every), ctypes.byref(self._nk(opts)), ctypes.byref(b)))
+        return b.value
+
+    def _cn_work(self, ckpt_every, opts):
+        nbytes = self.cn_workspace_bytes(max(int(ckpt_every), 1), opts)
+        return torch.empty(nbytes // (8 if self.dtype == torch.float64 else 4), dtype=self.dtype, device="cuda")
+
+    def cn_forward(self, u0, dt, nsteps, ckpt_every=0, opts=None, work=None):
+        """Crank-Nicolson with Newton-Krylov steps: (u(T), checkpoints or None, stats dict)."""
+        self._chk(u0, "u0")
+        u = u0.clone()
+        ck = None
+        if ckpt_every:
+            ck = torch.empty((nsteps // ckpt_every,) + self.shape, dtype=self.dtype, device="cuda")
+        work = self._cn_work(ckpt_every, opts) if work is None else work
+        st = NkStats()
+        self._bind()
+        _call(lib().sem_cn_forward(self._h, _ptr(u), float(dt), int(nsteps), int(ckpt_every),
+                                   _ptr(ck) if ck is not None else None, ctypes.byref(self._nk(opts)), _ptr(work),
+                                   ctypes.byref(st)))
+        return u, ck, st.as_dict()
+
+    def cn_adjoint(self, ckpt, dt, nsteps, ckpt_every, lamT, opts=None, work=None):
+        """Discrete Crank-Nicolson adjoint: (lambda_0, stats dict)."""
+        lam, _ = self._adjoint_args(ckpt, nsteps, ckpt_every, lamT, torch.empty(0, device="cuda"))
+        work = self._cn_work(ckpt_every, opts) if work is None else work
+        st = NkStats()
+        self._bind()
+        _call(lib().sem_cn_adjoint(self._h, _ptr(ckpt), float(dt), int(nsteps), int(ckpt_every), _ptr(lam),
+                                   ctypes.byref(self._nk(opts)), _ptr(work), ctypes.byref(st)))
+        return lam, st.as_dict()
+
     def rk_forward_revolve(self, u0, dt, nsteps, snaps, scheme="rk4"):
         """(u(T), snapshots [snaps][batch][C][...]) for binomial checkpointing with snaps slots."""
         self._chk(u0, "u0")
@@ -308,13 +366,16 @@ class SEMRhs(torch.autograd.Function):
 
 
 class SEMTrajectory(torch.autograd.Function):
-    """u(T) = Phi_dt^nsteps(u_0) for an explicit RK scheme ("rk4" or "rk3"), with backward by the
-    discrete adjoint of that scheme (Sec. 4.1) from uniform checkpoints every ckpt_every steps,
-    recomputed segment by segment (Sec. 5.3)."""
+    """u(T) = Phi_dt^nsteps(u_0) for a time integrator ("rk4", "rk3" or Crank-Nicolson "cn"), with
+    backward by the discrete adjoint of that scheme (Sec. 4.1) from uniform checkpoints every
+    ckpt_every steps, recomputed segment by segment (Sec. 5.3)."""
 
     @staticmethod
     def forward(ctx, u0, sem, dt, nsteps, ckpt_every, scheme="rk4"):
-        uT, ck = sem.rk_forward(u0.contiguous(), dt, nsteps, ckpt_every, scheme=scheme)
+        if scheme == "cn":
+            uT, ck, _ = sem.cn_forward(u0.contiguous(), dt, nsteps, ckpt_every)
+        else:
+            uT, ck = sem.rk_forward(u0.contiguous(), dt, nsteps, ckpt_every, scheme=scheme)
         ctx.sem, ctx.dt, ctx.nsteps, ctx.K, ctx.scheme = sem, dt, nsteps, ckpt_every, scheme
         ctx.save_for_backward(ck)
         return uT
@@ -322,7 +383,10 @@ class SEMTrajectory(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (ck,) = ctx.saved_tensors
-        lam0 = ctx.sem.rk_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous(), scheme=ctx.scheme)
+        if ctx.scheme == "cn":
+            lam0, _ = ctx.sem.cn_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous())
+        else:
+            lam0 = ctx.sem.rk_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous(), scheme=ctx.scheme)
         return lam0, None, None, None, None, None
 
 

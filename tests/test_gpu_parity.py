@@ -401,6 +401,67 @@ def test_revolve_trajectory_autograd(P):
 
 
 # ------------------------------------------------------------------------------------------------
+# Crank-Nicolson with Newton-Krylov steps and its discrete adjoint, vs the dense oracle
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,N,E,batch,n,K", [(1, 8, [16], 1, 10, 5), (2, 4, [3, 2], 2, 6, 3),
+                                               (3, 2, [2, 2, 2], 1, 4, 2), (3, 7, [4, 1, 1], 1, 2, 1)])
+def test_cn_forward_adjoint(P, dim, N, E, batch, n, K):
+    from oracle import cn as ocn
+    note(f"Crank-Nicolson dim={dim} N={N} E={E} batch={batch} steps={n}")
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    u, _, w = fields(m, 29)
+    dt = 2e-3 if dim > 1 else 1e-3
+    uT_ref, ck_ref = ocn.cn_forward(m, u, dt, n, K)
+    uT, ck, st = c.cn_forward(gpu(u), dt, n, K)
+    assert st["newton_iters"] >= n and st["max_rel_residual"] < 1e-10
+    assert rel(uT, uT_ref) < TOL_TRAJ
+    assert rel(ck, ck_ref) < TOL_TRAJ
+    lam_ref = ocn.cn_adjoint(m, ck_ref, dt, n, K, w)
+    lam, st = c.cn_adjoint(ck, dt, n, K, gpu(w))
+    assert st["linear_solves"] >= n
+    assert rel(lam, lam_ref) < TOL_TRAJ
+
+
+def test_cn_trajectory_gradient(P):
+    from oracle import cn as ocn
+    note("C1 mesh: Crank-Nicolson trajectory, autograd gradient vs oracle and finite differences")
+    m, u0, target = c1_inputs()
+    c = P.Context(1, wl.C1.N, wl.C1.E, wl.C1.L, wl.C1.nu)
+    dt, n, K = wl.C1_DT, 20, 5
+    x = gpu(u0).requires_grad_(True)
+    yT = P.trajectory(x, c, dt, n, K, scheme="cn")
+    loss = 0.5 * ((yT - gpu(target)) ** 2).sum()
+    loss.backward()
+    uT_ref, ck_ref = ocn.cn_forward(m, u0, dt, n, K)
+    phi_ref, lamT = m.misfit(uT_ref, target)
+    g_ref = ocn.cn_adjoint(m, ck_ref, dt, n, K, lamT)
+    assert abs(loss.item() - phi_ref[0]) < 1e-11 * abs(phi_ref[0])
+    assert rel(x.grad, g_ref) < TOL_TRAJ
+
+    def Phi(uu):
+        yy, _, _ = c.cn_forward(gpu(uu), dt, n)
+        return 0.5 * ((yy - gpu(target)) ** 2).sum().item()
+    g = x.grad.cpu().numpy()
+    for s in range(4):
+        d = wl.normal_field(m.shape, 300 + s)
+        eps = 1e-4 * np.linalg.norm(u0) / np.linalg.norm(d)
+        fd = (8 * (Phi(u0 + eps * d) - Phi(u0 - eps * d)) - (Phi(u0 + 2 * eps * d) - Phi(u0 - 2 * eps * d))) / (
+            12 * eps)
+        ad = float(np.vdot(g, d))
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (s, fd, ad)
+
+
+def test_cn_nonconvergence_is_reported(P):
+    note("Crank-Nicolson iteration limits")
+    m, c = make(P, 2, 4, [3, 2], nu=0.01)
+    u, _, _ = fields(m, 31)
+    with pytest.raises(P.SemError):
+        c.cn_forward(gpu(u), 2e-3, 2, opts={"newton_maxit": 1, "newton_rtol": 1e-30})
+    with pytest.raises(P.SemError):
+        c.cn_forward(gpu(u), 2e-3, 2, opts={"gmres_maxit": 1, "gmres_rtol": 1e-30})
+
+
+# ------------------------------------------------------------------------------------------------
 # Error handling at the boundary
 # ------------------------------------------------------------------------------------------------
 def test_errors(P):
