@@ -167,6 +167,21 @@ int sem_cn_forward(sem_ctx ctx, void* u, double dt, int32_t nsteps, int32_t ckpt
 /* lam in: lambda_N, out: lambda_0, from sem_cn_forward's checkpoints. */
 int sem_cn_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every, void* lam,
                    const sem_nk_opts* opts, void* work, sem_nk_stats* stats);
+/* Line search with guaranteed sufficient decrease (More and Thuente, the step-length rule of the
+   paper's LMVM optimiser, Sec. 5), host only, by reverse communication.  It seeks stp with
+   phi(stp) <= phi(0) + ftol stp phi'(0) and |phi'(stp)| <= gtol |phi'(0)|, stpmin <= stp <= stpmax.
+   Call first with *task = SEM_LS_START, f = phi(0), g = phi'(0) < 0 and *stp the initial step;
+   while it returns *task = SEM_LS_FG, evaluate f = phi(*stp), g = phi'(*stp) and call again.
+   It ends with SEM_LS_CONVERGED, SEM_LS_WARNING (no further progress: the interval reached xtol
+   relative width, rounding, or stp hit stpmin / stpmax; *stp is the best step) or SEM_LS_ERROR
+   (invalid start).  work/iwork carry the state between calls. */
+enum { SEM_LS_START = 0, SEM_LS_FG = 1, SEM_LS_CONVERGED = 2, SEM_LS_WARNING = 3, SEM_LS_ERROR = 4 };
+typedef struct {
+  double ftol, gtol, xtol, stpmin, stpmax; /* inputs */
+  double work[14];                         /* state, owned by the line search */
+  int32_t iwork[4];
+} sem_line_search;
+int sem_line_search_step(sem_line_search* ls, int32_t* task, double* stp, double f, double g);
 /* Bytes of caller work buffer needed by sem_rk4_adjoint / sem_rk_adjoint for a given ckpt_every. */
 int sem_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, int64_t* bytes);
 /* Enable (1) or disable (0, default) the non-finite check at the end of sem_rk4_forward (one
