@@ -620,3 +620,44 @@ def test_cn_checkpointing_is_bitwise_store_all():
         lams.append(ocn.cn_adjoint(m, ck, dt, n, K, lamT))
     np.testing.assert_array_equal(lams[0], lams[1])
     np.testing.assert_array_equal(lams[0], lams[2])
+
+
+# ------------------------------------------------------------------------------------------------
+# LMVM with More-Thuente steps (Sec. 5) and the 1-D optimal initial condition (Sec. 6.1)
+# ------------------------------------------------------------------------------------------------
+from oracle import lmvm as olmvm  # noqa: E402
+
+
+def recovery_problem(steps=800, dt=5e-3):
+    """Sec. 6.1: target = Cole-Hopf solution at T = 4 (a = 2), first guess = its initial condition
+    plus a Gaussian centred in the middle of the period-4 domain; nu = 0.01, E = 16, N = 8."""
+    nu = 0.01
+    m = oracle.Mesh(1, 8, [16], [4.0], nu)
+    x = m.coords(0)
+    exact0 = cole_hopf(x, 0.0, nu, 2.0)[None, None]
+    target = cole_hopf(x, steps * dt, nu, 2.0)[None, None]
+    guess = exact0 + np.exp(-4 * (x - 2) ** 2)[None, None]
+    return m, exact0, target, guess, dt, steps
+
+
+def test_lmvm_finds_the_minimiser_of_a_quadratic():
+    r = wl.rng(50)
+    Q, _ = np.linalg.qr(r.normal(size=(30, 30)))
+    A = Q @ np.diag(np.logspace(0, 2, 30)) @ Q.T
+    b = r.normal(size=30)
+    xs = np.linalg.solve(A, b)
+    x, hist, reason = olmvm.lmvm(lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b), np.zeros(30), max_iters=300,
+                                 gatol=1e-6)
+    # ||x - x*|| <= ||g|| / lambda_min = 1e-6 (eigenvalues in [1, 100])
+    assert reason == 1 and np.linalg.norm(x - xs) <= 1e-6
+    assert all(h1 < h0 for h0, h1 in zip(hist, hist[1:]))
+
+
+def test_lmvm_recovers_toward_the_initial_condition():
+    m, exact0, target, guess, dt, n = recovery_problem()
+    fg = olmvm.objective(m, "rk4", target, dt, n, 50)
+    x, hist, reason = olmvm.lmvm(fg, guess, max_iters=15)
+    assert reason == 3 and len(hist) == 16
+    assert all(h1 < h0 for h0, h1 in zip(hist, hist[1:]))
+    assert hist[-1] < 0.05 * hist[0]
+    assert np.abs(x - exact0).max() < 0.9 * np.abs(guess - exact0).max()
