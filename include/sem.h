@@ -49,7 +49,7 @@ typedef enum { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
 /* Explicit time integrators.  SEM_RK4: the classical four-stage method.  SEM_RK3: the three-stage
    explicit RK-3 of the paper's scalability runs (Sec. 6.3), which prints no tableau; libsem takes
    Kutta's third-order method (c = 0, 1/2, 1; a21 = 1/2, a31 = -1, a32 = 2; b = 1/6, 2/3, 1/6). */
-typedef enum { SEM_RK4 = 0, SEM_RK3 = 1 } sem_scheme;
+typedef enum { SEM_RK4 = 0, SEM_RK3 = 1, SEM_CN = 2 } sem_scheme;  /* SEM_CN: Crank-Nicolson (sem_cn_*) */
 
 /* Problem descriptor.  Supported: dim 1..3; order 1..12 for dim 1 and 2, 1..9 for dim 3;
    elems[k] >= 1; length[k] > 0; nu >= 0; batch >= 1.  Entries past dim are ignored. */
@@ -182,6 +182,33 @@ typedef struct {
   int32_t iwork[4];
 } sem_line_search;
 int sem_line_search_step(sem_line_search* ls, int32_t* task, double* stp, double f, double g);
+/* Optimal initial condition by LMVM (Sec. 5: limited-memory variable-metric directions with
+   More-Thuente step lengths; Sec. 6.1: recover u_0 from the state at time T).  Minimises
+   Phi(u_0) = 1/2 sum (u(T) - u*)^2 over all nodes, components and batch members, with u(T) from
+   `scheme` (SEM_RK4, SEM_RK3 or SEM_CN, nsteps of dt, checkpoints every ckpt_every) and the
+   gradient from its discrete adjoint.  Directions: -g first (tried with a step of length 1 in
+   the 2-norm), then the two-loop recursion over the last `memory` pairs (s, y) with s.y > 0 and
+   initial inverse Hessian (s.y / y.y) I, tried with step 1; a direction that does not descend
+   restarts from -g.  u0: in the initial guess, out the final iterate.  work: device buffer of
+   sem_lmvm_workspace_bytes bytes.  history (host, may be NULL) receives Phi at iterates 0..iters.
+   Synchronises the stream. */
+typedef struct {
+  int32_t max_iters;       /* 0: 50 */
+  int32_t memory;          /* stored pairs, 1..20; 0: 5 */
+  double gatol, grtol;     /* stop when ||g||_2 <= gatol or <= grtol |Phi|; 0: 1e-10 each */
+  double ftol, gtol, xtol; /* line search (sem_line_search); 0: 1e-4, 0.9, 1e-10 */
+  int32_t max_evals;       /* evaluations per line search; 0: 30 */
+} sem_lmvm_opts;
+typedef struct {
+  int32_t iters, evals;  /* iterations, objective-and-gradient evaluations */
+  int32_t reason;        /* 1 gatol, 2 grtol, 3 max_iters; -1 line search failed or exhausted */
+  double f0, f, gnorm;   /* first and last Phi, last ||g||_2 */
+} sem_lmvm_stats;
+int sem_lmvm_workspace_bytes(sem_ctx ctx, int32_t scheme, int32_t nsteps, int32_t ckpt_every,
+                             const sem_lmvm_opts* opts, int64_t* bytes);
+int sem_lmvm_initial_condition(sem_ctx ctx, int32_t scheme, void* u0, const void* target, double dt, int32_t nsteps,
+                               int32_t ckpt_every, const sem_lmvm_opts* opts, void* work, double* history,
+                               sem_lmvm_stats* stats);
 /* Bytes of caller work buffer needed by sem_rk4_adjoint / sem_rk_adjoint for a given ckpt_every. */
 int sem_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, int64_t* bytes);
 /* Enable (1) or disable (0, default) the non-finite check at the end of sem_rk4_forward (one

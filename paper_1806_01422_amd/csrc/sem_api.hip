@@ -800,6 +800,158 @@ struct Implicit {
   }
 };
 
+// LMVM for the optimal initial condition: device vectors in one work buffer, host scalars.
+struct Lmvm {
+  Integrator* in = nullptr;
+  Implicit* im = nullptr;  // set for SEM_CN
+  int scheme = SEM_RK4;
+  hipStream_t s = nullptr;
+  double* partial = nullptr;
+  double* dvec = nullptr;
+  int32_t nsteps = 0, K = 1;
+  const void* target = nullptr;
+  char* ckpt = nullptr;   // nsteps / K states
+  char* adjw = nullptr;   // adjoint work
+  char* resid = nullptr;  // u(T) - u*
+  int evals = 0;
+
+  int dtype() const { return in->os->dtype; }
+  size_t bytes() const { return (size_t)in->n * in->ts; }
+
+  int dot(const void* a, const void* b, double* r) {
+    HIPCHK(blas_multidot(dtype(), a, in->n, 1, b, in->n, partial, dvec, s));
+    HIPCHK(hipMemcpyAsync(r, dvec, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SEM_OK;
+  }
+  hipError_t axpby(void* z, double a, const void* x, double b, const void* y) {
+    return blas_axpby(dtype(), z, a, x, b, y, in->n, s);
+  }
+
+  // Phi(x) and its gradient g (discrete adjoint of the scheme)
+  int evaluate(const void* x, void* g, double* f) {
+    ++evals;
+    HIPCHK(hipMemcpyAsync(resid, x, bytes(), hipMemcpyDeviceToDevice, s));
+    int rc = im ? im->forward(resid, nsteps, K, ckpt, adjw) : in->forward(scheme, resid, nsteps, K, ckpt, s);
+    if (rc) return rc;
+    HIPCHK(axpby(resid, 1.0, resid, -1.0, target));
+    double rr = 0;
+    if ((rc = dot(resid, resid, &rr))) return rc;
+    *f = 0.5 * rr;
+    if (!std::isfinite(*f)) return fail(SEM_ERR_NONFINITE, "non-finite objective (dt too large?)");
+    HIPCHK(hipMemcpyAsync(g, resid, bytes(), hipMemcpyDeviceToDevice, s));
+    rc = im ? im->adjoint(ckpt, nsteps, K, g, adjw) : in->adjoint(scheme, ckpt, nsteps, K, g, adjw, s);
+    return rc;
+  }
+
+  int run(void* u0, char* vecs, int memory, const sem_lmvm_opts& o, double* history, sem_lmvm_stats& st) {
+    const size_t B = bytes();
+    char* x = vecs;
+    char* g = vecs + B;
+    char* d = vecs + 2 * B;
+    char* xt = vecs + 3 * B;
+    char* gt = vecs + 4 * B;
+    char* tmp = vecs + 5 * B;
+    char* S = vecs + 6 * B;                        // memory pairs: S_i, then Y_i
+    char* Y = S + (size_t)memory * B;
+    std::vector<double> rho(memory), alpha(memory);
+    int npairs = 0, newest = -1;
+    HIPCHK(hipMemcpyAsync(x, u0, B, hipMemcpyDeviceToDevice, s));
+    double f = 0, gn = 0;
+    int rc = evaluate(x, g, &f);
+    if (rc) return rc;
+    st.f0 = f;
+    if (history) history[0] = f;
+    st.reason = 0;
+    int k = 0;
+    for (;; ++k) {
+      double gg = 0;
+      if ((rc = dot(g, g, &gg))) return rc;
+      gn = std::sqrt(gg);
+      if (gn <= o.gatol) { st.reason = 1; break; }
+      if (gn <= o.grtol * std::fabs(f)) { st.reason = 2; break; }
+      if (k >= o.max_iters) { st.reason = 3; break; }
+      // direction: two-loop recursion (or steepest descent when no pair is stored)
+      double stp0 = 1.0;
+      HIPCHK(hipMemcpyAsync(d, g, B, hipMemcpyDeviceToDevice, s));
+      if (npairs > 0) {
+        for (int c = 0, i = newest; c < npairs; ++c, i = (i - 1 + memory) % memory) {
+          double sq = 0;
+          if ((rc = dot(S + (size_t)i * B, d, &sq))) return rc;
+          alpha[i] = rho[i] * sq;
+          HIPCHK(axpby(d, 1.0, d, -alpha[i], Y + (size_t)i * B));
+        }
+        double sy = 0, yy = 0;
+        if ((rc = dot(S + (size_t)newest * B, Y + (size_t)newest * B, &sy)) ||
+            (rc = dot(Y + (size_t)newest * B, Y + (size_t)newest * B, &yy)))
+          return rc;
+        HIPCHK(axpby(d, sy / yy, d, 0.0, nullptr));
+        const int oldest = (newest - npairs + 1 + memory) % memory;
+        for (int c = 0, i = oldest; c < npairs; ++c, i = (i + 1) % memory) {
+          double yr = 0;
+          if ((rc = dot(Y + (size_t)i * B, d, &yr))) return rc;
+          HIPCHK(axpby(d, 1.0, d, alpha[i] - rho[i] * yr, S + (size_t)i * B));
+        }
+      }
+      HIPCHK(axpby(d, -1.0, d, 0.0, nullptr));
+      double gd = 0;
+      if ((rc = dot(g, d, &gd))) return rc;
+      if (npairs == 0 || !(gd < 0)) {  // steepest descent, first step of unit length
+        if (npairs > 0) HIPCHK(axpby(d, -1.0, g, 0.0, nullptr));
+        npairs = 0, newest = -1;
+        gd = -gg;
+        stp0 = 1.0 / gn;
+      }
+      // More-Thuente line search on phi(t) = Phi(x + t d)
+      sem_line_search ls{};
+      ls.ftol = o.ftol, ls.gtol = o.gtol, ls.xtol = o.xtol, ls.stpmin = 0.0, ls.stpmax = 1e10;
+      int32_t task = SEM_LS_START;
+      double stp = stp0, last = -1.0, ft = f;
+      sem_line_search_step(&ls, &task, &stp, f, gd);
+      int n_eval = 0;
+      while (task == SEM_LS_FG && n_eval < o.max_evals) {
+        HIPCHK(axpby(xt, 1.0, x, stp, d));
+        if ((rc = evaluate(xt, gt, &ft))) return rc;
+        double gtd = 0;
+        if ((rc = dot(gt, d, &gtd))) return rc;
+        last = stp;
+        ++n_eval;
+        sem_line_search_step(&ls, &task, &stp, ft, gtd);
+      }
+      if (task != SEM_LS_CONVERGED && task != SEM_LS_WARNING) { st.reason = -1; break; }
+      if (stp != last) {  // the line search settled on its best earlier step
+        HIPCHK(axpby(xt, 1.0, x, stp, d));
+        if ((rc = evaluate(xt, gt, &ft))) return rc;
+      }
+      if (!(ft < f)) { st.reason = -1; break; }
+      // new pair s = xt - x, y = gt - g (into scratch: the direction is spent), kept if s.y > 0
+      HIPCHK(axpby(d, 1.0, xt, -1.0, x));
+      HIPCHK(axpby(tmp, 1.0, gt, -1.0, g));
+      double sy = 0;
+      if ((rc = dot(d, tmp, &sy))) return rc;
+      if (sy > 0) {
+        const int slot = (newest + 1) % memory;
+        HIPCHK(hipMemcpyAsync(S + (size_t)slot * B, d, B, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(Y + (size_t)slot * B, tmp, B, hipMemcpyDeviceToDevice, s));
+        rho[slot] = 1.0 / sy;
+        newest = slot;
+        npairs = std::min(npairs + 1, memory);
+      }
+      std::swap(x, xt);
+      std::swap(g, gt);
+      f = ft;
+      if (history) history[k + 1] = f;
+    }
+    st.iters = k;
+    st.evals = evals;
+    st.f = f;
+    st.gnorm = gn;
+    HIPCHK(hipMemcpyAsync(u0, x, B, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return SEM_OK;
+  }
+};
+
 }  // namespace
 
 struct sem_ctx_s {
@@ -1018,6 +1170,75 @@ int sem_cn_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32
   if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
   rc = im.adjoint(ckpt, nsteps, K, lam, static_cast<char*>(work));
   if (stats) *stats = im.st;
+  return rc;
+}
+
+static sem_lmvm_opts lmvm_defaults(const sem_lmvm_opts* o) {
+  sem_lmvm_opts r{};
+  r.max_iters = (o && o->max_iters > 0) ? o->max_iters : 50;
+  r.memory = (o && o->memory > 0) ? o->memory : 5;
+  r.gatol = (o && o->gatol > 0) ? o->gatol : 1e-10;
+  r.grtol = (o && o->grtol > 0) ? o->grtol : 1e-10;
+  r.ftol = (o && o->ftol > 0) ? o->ftol : 1e-4;
+  r.gtol = (o && o->gtol > 0) ? o->gtol : 0.9;
+  r.xtol = (o && o->xtol > 0) ? o->xtol : 1e-10;
+  r.max_evals = (o && o->max_evals > 0) ? o->max_evals : 30;
+  return r;
+}
+
+// states of the LMVM work buffer: 6 iterate/scratch vectors, 2 m pairs, the residual, the checkpoints and
+// the adjoint work of the scheme
+static int64_t lmvm_states(int32_t scheme, int32_t nsteps, int32_t K, const sem_lmvm_opts& o) {
+  const int64_t adj = scheme == SEM_CN ? (int64_t)K + 1 + 30 + 2 : (int64_t)K;
+  return 6 + 2 * (int64_t)o.memory + 1 + nsteps / K + adj;
+}
+
+int sem_lmvm_workspace_bytes(sem_ctx c, int32_t scheme, int32_t nsteps, int32_t K, const sem_lmvm_opts* opts,
+                             int64_t* bytes) {
+  if (!c || !bytes) return fail(SEM_ERR_ARG, "null argument");
+  if (scheme != SEM_RK4 && scheme != SEM_RK3 && scheme != SEM_CN) return fail(SEM_ERR_ARG, "unknown scheme %d", scheme);
+  if (int rc = check_steps(1.0, nsteps, K, true)) return rc;
+  const sem_lmvm_opts o = lmvm_defaults(opts);
+  *bytes = lmvm_states(scheme, nsteps, K, o) * c->integ.n * (int64_t)c->os.ts;
+  return SEM_OK;
+}
+
+int sem_lmvm_initial_condition(sem_ctx c, int32_t scheme, void* u0, const void* target, double dt, int32_t nsteps,
+                               int32_t K, const sem_lmvm_opts* opts, void* work, double* history,
+                               sem_lmvm_stats* stats) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!u0 || !target || !work) return fail(SEM_ERR_ARG, "null pointer");
+  if (u0 == target || work == u0 || work == target) return fail(SEM_ERR_ARG, "aliased buffers");
+  if (scheme != SEM_RK4 && scheme != SEM_RK3 && scheme != SEM_CN) return fail(SEM_ERR_ARG, "unknown scheme %d", scheme);
+  int rc = check_steps(dt, nsteps, K, true);
+  if (rc) return rc;
+  if (nsteps < 1) return fail(SEM_ERR_ARG, "nsteps must be >= 1");
+  const sem_lmvm_opts o = lmvm_defaults(opts);
+  if (o.memory > 20) return fail(SEM_ERR_ARG, "memory %d > 20", o.memory);
+  Implicit im;
+  Lmvm L;
+  L.in = &c->integ;
+  L.scheme = scheme;
+  L.s = c->stream;
+  L.partial = static_cast<double*>(c->nk.p);
+  L.dvec = reinterpret_cast<double*>(static_cast<char*>(c->nk.p) + blas_partial_bytes());
+  if (scheme == SEM_CN) {
+    if ((rc = cn_setup(c, nullptr, im))) return rc;
+    L.im = &im;
+  } else if ((rc = c->integ.prepare(scheme))) {
+    return rc;
+  }
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  L.nsteps = nsteps, L.K = K, L.target = target;
+  const size_t B = (size_t)c->integ.n * c->os.ts;
+  char* w = static_cast<char*>(work);
+  char* vecs = w;
+  L.resid = w + (size_t)(6 + 2 * o.memory) * B;
+  L.ckpt = L.resid + B;
+  L.adjw = L.ckpt + (size_t)(nsteps / K) * B;
+  sem_lmvm_stats st{};
+  rc = L.run(u0, vecs, o.memory, o, history, st);
+  if (stats) *stats = st;
   return rc;
 }
 

@@ -18,6 +18,7 @@ SEM_F64, SEM_F32 = 0, 1
 
 # time-integration schemes (sem_scheme): classical RK4 and the three-stage RK-3 (Kutta's tableau)
 SCHEMES = {"rk4": 0, "rk3": 1}
+_ALL_SCHEMES = {"rk4": 0, "rk3": 1, "cn": 2}
 
 
 def _scheme(name):
@@ -36,6 +37,22 @@ class NkStats(ctypes.Structure):
     """sem_nk_stats: iteration counts of a Crank-Nicolson call."""
     _fields_ = [("newton_iters", ctypes.c_int64), ("linear_solves", ctypes.c_int64), ("gmres_iters", ctypes.c_int64),
                 ("max_rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LmvmOpts(ctypes.Structure):
+    """sem_lmvm_opts (zeros select defaults)."""
+    _fields_ = [("max_iters", ctypes.c_int32), ("memory", ctypes.c_int32), ("gatol", ctypes.c_double),
+                ("grtol", ctypes.c_double), ("ftol", ctypes.c_double), ("gtol", ctypes.c_double),
+                ("xtol", ctypes.c_double), ("max_evals", ctypes.c_int32)]
+
+
+class LmvmStats(ctypes.Structure):
+    """sem_lmvm_stats."""
+    _fields_ = [("iters", ctypes.c_int32), ("evals", ctypes.c_int32), ("reason", ctypes.c_int32),
+                ("f0", ctypes.c_double), ("f", ctypes.c_double), ("gnorm", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +99,9 @@ _SIGS = {
     "sem_cn_workspace_bytes": [_vp, _i32, _vp, _vp],
     "sem_cn_forward": [_vp, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
     "sem_cn_adjoint": [_vp, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
+    "sem_lmvm_workspace_bytes": [_vp, _i32, _i32, _i32, _vp, _vp],
+    "sem_lmvm_initial_condition": [_vp, _i32, _vp, _vp, _f64, _i32, _i32, _vp, _vp, _vp, _vp],
+    "sem_line_search_step": [_vp, _vp, _vp, _f64, _f64],
     "sem_rk_forward": [_vp, _i32, _vp, _f64, _i32, _i32, _vp],
     "sem_rk_adjoint": [_vp, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
     "sem_batch_rk_forward": [_vp, _i32, _vp, _i32, _i32, _vp],
@@ -311,6 +331,30 @@ class Context:
         _call(lib().sem_cn_adjoint(self._h, _ptr(ckpt), float(dt), int(nsteps), int(ckpt_every), _ptr(lam),
                                    ctypes.byref(self._nk(opts)), _ptr(work), ctypes.byref(st)))
         return lam, st.as_dict()
+
+    def lmvm_initial_condition(self, u0, target, dt, nsteps, ckpt_every, scheme="rk4", opts=None, work=None):
+        """Minimise 1/2 ||u(T; u_0) - target||^2 over u_0 by LMVM with More-Thuente steps, starting
+        from u0: (u_0 found, history of the objective per iteration, stats dict)."""
+        self._chk(u0, "u0")
+        self._chk(target, "target")
+        if scheme not in _ALL_SCHEMES:
+            raise SemError(f"unknown scheme {scheme!r}")
+        o = LmvmOpts()
+        for k, v in (opts or {}).items():
+            setattr(o, k, v)
+        if work is None:
+            b = _i64()
+            _call(lib().sem_lmvm_workspace_bytes(self._h, _ALL_SCHEMES[scheme], int(nsteps), int(ckpt_every),
+                                                 ctypes.byref(o), ctypes.byref(b)))
+            work = torch.empty(b.value // (8 if self.dtype == torch.float64 else 4), dtype=self.dtype, device="cuda")
+        u = u0.clone()
+        hist = (ctypes.c_double * ((o.max_iters or 50) + 1))()
+        st = LmvmStats()
+        self._bind()
+        _call(lib().sem_lmvm_initial_condition(self._h, _ALL_SCHEMES[scheme], _ptr(u), _ptr(target), float(dt),
+                                               int(nsteps), int(ckpt_every), ctypes.byref(o), _ptr(work), hist,
+                                               ctypes.byref(st)))
+        return u, list(hist[: st.iters + 1]), st.as_dict()
 
     def rk_forward_revolve(self, u0, dt, nsteps, snaps, scheme="rk4"):
         """(u(T), snapshots [snaps][batch][C][...]) for binomial checkpointing with snaps slots."""

@@ -5,6 +5,7 @@ norm-wise as max|x - x_ref| / max|x_ref| (fields cross zero, so element-wise rel
 meaningful).  FP32 results are compared with the FP64 oracle at 1e-4 (rounding of 8-point
 contractions in single precision, ~1e-6 expected).
 """
+import os
 import sys
 
 import numpy as np
@@ -13,6 +14,8 @@ import torch
 
 import oracle
 import workloads as wl
+
+sys.path.insert(0, os.path.dirname(__file__))
 
 pytestmark = pytest.mark.gpu
 
@@ -459,6 +462,40 @@ def test_cn_nonconvergence_is_reported(P):
         c.cn_forward(gpu(u), 2e-3, 2, opts={"newton_maxit": 1, "newton_rtol": 1e-30})
     with pytest.raises(P.SemError):
         c.cn_forward(gpu(u), 2e-3, 2, opts={"gmres_maxit": 1, "gmres_rtol": 1e-30})
+
+
+# ------------------------------------------------------------------------------------------------
+# LMVM optimal initial condition (Sec. 5, Sec. 6.1) vs the oracle's LMVM
+# ------------------------------------------------------------------------------------------------
+def lmvm_case(steps, dt=5e-3):
+    import test_oracle as to
+    return to.recovery_problem(steps, dt)
+
+
+def test_lmvm_recovery_matches_oracle(P):
+    from oracle import lmvm as olmvm
+    note("LMVM: 1-D optimal initial condition, RK4, 15 iterations")
+    m, exact0, target, guess, dt, n = lmvm_case(800)
+    c = P.Context(1, 8, [16], [4.0], 0.01)
+    u, hist, st = c.lmvm_initial_condition(gpu(guess), gpu(target), dt, n, 50, scheme="rk4", opts={"max_iters": 15})
+    x_ref, h_ref, reason = olmvm.lmvm(olmvm.objective(m, "rk4", target, dt, n, 50), guess, max_iters=15)
+    assert st["reason"] == reason == 3 and st["iters"] == 15
+    np.testing.assert_allclose(hist, h_ref, rtol=1e-8)
+    assert rel(u, x_ref) < 1e-7
+    assert hist[-1] < 0.05 * hist[0]
+
+
+@pytest.mark.parametrize("scheme", ["rk3", "cn"])
+def test_lmvm_other_schemes(P, scheme):
+    from oracle import lmvm as olmvm
+    note(f"LMVM with {scheme}, 4 iterations")
+    m, exact0, target, guess, dt, n = lmvm_case(40)
+    c = P.Context(1, 8, [16], [4.0], 0.01)
+    u, hist, st = c.lmvm_initial_condition(gpu(guess), gpu(target), dt, n, 10, scheme=scheme, opts={"max_iters": 4})
+    x_ref, h_ref, reason = olmvm.lmvm(olmvm.objective(m, scheme, target, dt, n, 10), guess, max_iters=4)
+    assert st["reason"] == reason
+    np.testing.assert_allclose(hist, h_ref, rtol=1e-8)
+    assert rel(u, x_ref) < 1e-7
 
 
 # ------------------------------------------------------------------------------------------------
