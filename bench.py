@@ -187,6 +187,99 @@ def rk_adjoint_ratio(P, nsteps=10):
     return out
 
 
+def revolve_measure(P, nsteps=40):
+    """RK-3 on the 3-D 32^3 N=7 FP64 field with binomial checkpointing in a few state slots:
+    forward and adjoint time per step, forward steps the schedule recomputes, memory in states."""
+    cfg = wl.C3
+    ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
+    U, _, W = c3_inputs(ctx, torch.float64)
+    dt = 1e-4
+    out = {"workload": f"3-D 32^3 N=7 FP64, RK-3, {nsteps} steps, dt={dt}"}
+    for snaps in (4, 8):
+        _, adv = P.revolve_plan(nsteps, snaps)
+        uT, ck = ctx.rk_forward_revolve(U, dt, nsteps, snaps, scheme="rk3")
+        work = torch.empty(ctx.workspace_bytes(1) * snaps // 8, dtype=torch.float64, device="cuda")
+        t_f = event_time_ms(lambda: ctx.rk_forward_revolve(U, dt, nsteps, snaps, scheme="rk3"), 2) / nsteps
+        t_a = event_time_ms(lambda: ctx.rk_adjoint_revolve(ck, dt, nsteps, snaps, W, scheme="rk3", work=work),
+                            2) / nsteps
+        out[f"snaps{snaps}"] = {"forward_ms_per_step": round(t_f, 4), "adjoint_ms_per_step": round(t_a, 4),
+                                "adjoint_over_forward": round(t_a / t_f, 3), "schedule_forward_steps": adv,
+                                "state_slots": snaps, "store_all_states": nsteps}
+        del ck, work
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def cn_measure(P, nsteps=4, K=2, dt=2e-4):
+    """Crank-Nicolson on the 3-D 32^3 N=7 FP64 field: forward (Newton-Krylov per step) and
+    discrete adjoint (one GMRES solve with J^T per step plus the segment recompute)."""
+    cfg = wl.C3
+    ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
+    U, _, W = c3_inputs(ctx, torch.float64)
+    work = torch.empty(ctx.cn_workspace_bytes(K) // 8, dtype=torch.float64, device="cuda")
+    uT, ck, _ = ctx.cn_forward(U, dt, nsteps, K, work=work)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uT, ck, sf = ctx.cn_forward(U, dt, nsteps, K, work=work)
+    t_f = (time.perf_counter() - t0) * 1e3 / nsteps
+    t0 = time.perf_counter()
+    lam, sa = ctx.cn_adjoint(ck, dt, nsteps, K, W, work=work)
+    t_a = (time.perf_counter() - t0) * 1e3 / nsteps
+    ctx.close()
+    del U, W, work, ck, uT, lam
+    torch.cuda.empty_cache()
+    return {"workload": f"3-D 32^3 N=7 FP64, Crank-Nicolson, {nsteps} steps, dt={dt}, checkpoint every {K}",
+            "forward_ms_per_step": round(t_f, 3), "adjoint_ms_per_step": round(t_a, 3),
+            "adjoint_over_forward": round(t_a / t_f, 3), "forward_stats": sf, "adjoint_stats": sa,
+            "note": "the adjoint includes recomputing each segment's states (Newton solves)"}
+
+
+def lmvm_measure(P):
+    """The optimiser on the GPU: (a) the 1-D optimal-initial-condition recovery (Cole-Hopf target at
+    T = 4, Gaussian-perturbed first guess, E=16 N=8 nu=0.01, RK4 dt=5e-3, 30 iterations); (b) five
+    LMVM iterations on the 3-D 16^3 N=7 mesh (4,214,784 DOF, the small scalability case) with RK-3,
+    20 steps of dt=1e-4, checkpoint every 5 steps, recovering a seeded Fourier field from its
+    state at T."""
+    out = {}
+    nu, T, dt = 0.01, 4.0, 5e-3
+    c = P.Context(1, 8, [16], [4.0], nu)
+    x = torch.from_numpy(c.node_coords(0))
+
+    def ch(t):
+        ex = np.exp(-nu * np.pi ** 2 * t)
+        return 2 * nu * np.pi * torch.sin(np.pi * x) * ex / (2.0 + ex * torch.cos(np.pi * x))
+    exact0 = ch(0.0)[None, None].to("cuda", torch.float64)
+    target = ch(T)[None, None].to("cuda", torch.float64)
+    guess = exact0 + torch.exp(-4 * (x - 2) ** 2)[None, None].to("cuda", torch.float64)
+    n = int(round(T / dt))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, hist, st = c.lmvm_initial_condition(guess, target, dt, n, 50, scheme="rk4", opts={"max_iters": 30})
+    t1 = time.perf_counter() - t0
+    out["recovery_1d"] = {"iterations": st["iters"], "evaluations": st["evals"], "seconds": round(t1, 3),
+                          "objective": [hist[0], hist[5], hist[10], hist[-1]],
+                          "ic_error_l2_relative": float((u - exact0).norm() / (guess - exact0).norm())}
+    c.close()
+    cfg = wl.C3
+    ctx = P.Context(3, cfg.N, [16, 16, 16], cfg.L, cfg.nu, dtype=torch.float64)
+    xs = [ctx.node_coords(k) for k in range(3)]
+    dev = lambda a: torch.from_numpy(a).to("cuda", torch.float64)  # noqa: E731
+    truth = dev(wl.fourier_field(xs, cfg.L, wl.C3_K, 30)[None])
+    target, _ = ctx.rk_forward(truth, 1e-4, 20, scheme="rk3")
+    guess = dev(wl.fourier_field(xs, cfg.L, wl.C3_K, 31)[None])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, hist, st = ctx.lmvm_initial_condition(guess, target, 1e-4, 20, 5, scheme="rk3", opts={"max_iters": 5})
+    t2 = time.perf_counter() - t0
+    out["small_case_3d"] = {"dof": ctx.ndof, "iterations": st["iters"], "evaluations": st["evals"],
+                            "seconds": round(t2, 3), "seconds_per_evaluation": round(t2 / st["evals"], 4),
+                            "objective": [hist[0], hist[-1]]}
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +387,12 @@ def main():
         log("c5 done")
         out["rk_adjoint"] = rk_adjoint_ratio(P)
         log("rk adjoint ratio done")
+        out["revolve"] = revolve_measure(P)
+        log("revolve done")
+        out["crank_nicolson"] = cn_measure(P)
+        log("crank-nicolson done")
+        out["lmvm"] = lmvm_measure(P)
+        log("lmvm done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
         log("cpu baseline done")
