@@ -30,12 +30,12 @@
 //      the x = 28X node still lacks the left neighbour's part).  fast3d_fixup adds the parts,
 //      applies the inverse mass and the epilogue, and writes those nodes as whole row segments
 //      and whole sectors, so no 32-byte sector of the output is written twice.
-#include "sem_internal.h"
+#include "fast_common.h"
 
 namespace sem {
 namespace {
 
-constexpr int NQ = 7;  // order
+using namespace fast;
 constexpr int WX = 4;  // elements per workgroup along x, one per wavefront
 // Face buffer of one batch member: four regions, each [workgroup][component][grid plane z][width]
 // so that every region is read by one neighbour's fixup as a run contiguous in z.
@@ -49,16 +49,6 @@ constexpr int O_LY = 0, O_UY = 28, O_UX = 57, O_LX = 64;
 constexpr int FROWS = 88;  // total width
 constexpr int FSEC = 13;   // 32-byte sectors the fixup completes per (workgroup, component, z): 7 + 6
 
-// The even/odd blocks of D are A[i][m] = (D_im - D_i,7-m)/2 and B[i][m] = (D_im + D_i,7-m)/2
-// (i, m < 4).  Centro-antisymmetry makes the blocks of D^T their transposes (A' = B^T, B' = A^T),
-// so one 32-entry table serves both contractions.
-template <typename T>
-struct FastTab {
-  T A[16], B[16];
-  T w[8];            // GLL weights
-  T imq[8];          // 1 / (assembled 1-D reference mass at local index q): 1/(2 w_0) at q = 0, 7
-};
-
 struct FastArgs {
   int Ex, Ey, Ez, nx, ny, nz;
   int NX, NWG;  // workgroups along x (Ex / 4) and per field (NX * Ey)
@@ -68,160 +58,11 @@ struct FastArgs {
   const ProbDev* prob;
 };
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Raw buffer accesses: a lane whose byte offset is out of range (OOB) stores nothing and loads 0,
-// so lane predicates become offsets and the store sequence stays free of branches (which keeps
-// the compiler's wait counts exact: loads and stores share one counter on this architecture).
-typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-constexpr uint32_t OOB = 0x80000000u;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
-}
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, (int)off, 0, 0);
-}
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)off, 0, 0);
-}
-template <typename T>
-__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  if constexpr (sizeof(T) == 8)
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-  else
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-}
-
 // Swizzled LDS tile index of element-local point (a, b, c): (c, b ^ c, a ^ b).  In each of the
 // three maps (lanes over (a, b), (a, c) or (b, c)) every group of 32 consecutive lanes hits 32
 // distinct 8-byte bank pairs, so 64-bit accesses are free of bank conflicts with 64 banks (and
 // 32-bit accesses with all 64 lanes at once).
 __device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b ^ c) << 3) + (a ^ b); }
-
-// y = D x (TR = false) or y = D^T x (TR = true) on one 8-point line, even/odd split:
-//   e_m = x_m + x_{7-m}, o_m = x_m - x_{7-m};  y_i = s_i + d_i, y_{7-i} = s_i - d_i  (i < 4)
-//   D:   s_i = sum_m A[i][m] o_m,  d_i = sum_m B[i][m] e_m
-//   D^T: s_i = sum_m B[m][i] o_m,  d_i = sum_m A[m][i] e_m
-template <bool TR, typename T>
-__device__ __forceinline__ void contract(const T (&x)[8], T (&y)[8], const FastTab<T>* __restrict__ tb) {
-  const T e0 = x[0] + x[7], e1 = x[1] + x[6], e2 = x[2] + x[5], e3 = x[3] + x[4];
-  const T o0 = x[0] - x[7], o1 = x[1] - x[6], o2 = x[2] - x[5], o3 = x[3] - x[4];
-  const T* __restrict__ A = tb->A;
-  const T* __restrict__ B = tb->B;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    T s, d;
-    if constexpr (!TR) {
-      s = A[4 * i] * o0 + A[4 * i + 1] * o1 + A[4 * i + 2] * o2 + A[4 * i + 3] * o3;
-      d = B[4 * i] * e0 + B[4 * i + 1] * e1 + B[4 * i + 2] * e2 + B[4 * i + 3] * e3;
-    } else {
-      s = B[i] * o0 + B[4 + i] * o1 + B[8 + i] * o2 + B[12 + i] * o3;
-      d = A[i] * e0 + A[4 + i] * e1 + A[8 + i] * e2 + A[12 + i] * e3;
-    }
-    y[i] = s + d;
-    y[7 - i] = s - d;
-  }
-}
-
-// Contribution of direction j (the lane's register direction) to the element residual of every
-// component.  ldU(i, U) / ldV(i, V) fill the 8 register values of component i of the state and of
-// the direction (J v) or scaled adjoint input Z = M^{-1} w (J^T) in the current map; emit(i, P)
-// receives the contribution to component i.  om[s] is the quadrature weight at register s,
-// K1 = nu sc_j^2, K2 = sc_j (the 2/h_j of D on the physical element folded in).
-template <typename T, int OP, typename LU, typename LV, typename EM>
-__device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const T (&om)[8], T K1, T K2,
-                                            const FastTab<T>* __restrict__ tb, EM emit) {
-  T c1[8], cu[8];
-  {
-    T Uj[8];
-    ldU(j, Uj);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      c1[s] = K1 * om[s];
-      cu[s] = K2 * om[s] * Uj[s];
-    }
-  }
-  if constexpr (OP == OP_RHS) {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      T Ui[8], G[8], f[8], t[8];
-      ldU(i, Ui);
-      contract<false>(Ui, G, tb);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) f[s] = c1[s] * G[s];
-      contract<true>(f, t, tb);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) t[s] = -(t[s] + cu[s] * G[s]);
-      emit(i, t);
-    }
-  } else if constexpr (OP == OP_JAC) {
-    T cv[8];
-    {
-      T Vj[8];
-      ldV(j, Vj);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) cv[s] = K2 * om[s] * Vj[s];
-    }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      T X[8], G[8], H[8], t[8];
-      ldU(i, X);
-      contract<false>(X, G, tb);
-      ldV(i, X);
-      contract<false>(X, H, tb);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) X[s] = c1[s] * H[s];
-      contract<true>(X, t, tb);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) t[s] = -(t[s] + cv[s] * G[s] + cu[s] * H[s]);
-      emit(i, t);
-    }
-  } else {  // OP_JACT: V holds Z = M^{-1} w
-    T acc[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) acc[s] = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      T X[8], G[8];
-      ldU(i, X);
-      contract<false>(X, G, tb);
-      ldV(i, X);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) acc[s] += X[s] * G[s];
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s) acc[s] *= K2 * om[s];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      T Zl[8], H[8], t[8];
-      ldV(l, Zl);
-      contract<false>(Zl, H, tb);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) H[s] = c1[s] * H[s] + cu[s] * Zl[s];
-      contract<true>(H, t, tb);
-#pragma unroll
-      for (int s = 0; s < 8; ++s) t[s] = (l == j) ? -(t[s] + acc[s]) : -t[s];
-      emit(l, t);
-    }
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T coef(const Coef& c, double dt) {
-  return (T)(c.c0 + c.cdt * dt);
-}
-
-// Workgroup (X, ey) of block `bid`.  Blocks are dealt round-robin to the 8 XCDs; when the count
-// allows, consecutive logical workgroups are given to the same XCD so that it sweeps a contiguous
-// band of element rows and its L2 serves the rows shared by neighbouring workgroups.
-__device__ __forceinline__ int logical_wg(int bid, int nwg) {
-  return (nwg % 8 == 0) ? (bid % 8) * (nwg / 8) + bid / 8 : bid;
-}
 
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
 // 2 = o1 = a1 x1 + c1 x2 + b1 s and (when o2 is given) o2 = a2 x2 + c2 x1 + b2 s.
@@ -370,7 +211,7 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
         tU[i * 512 + tix(l0, l1, c)] = cu[i][c];
         if constexpr (HASV) tV[i * 512 + tix(l0, l1, c)] = cv[i][c];
       }
-    map_contrib<T, OP>(
+    map_contrib<T, OP, 3>(
         2,
         [&](int i, T (&Xr)[8]) {
 #pragma unroll
@@ -396,7 +237,7 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
     load_z(ez + 1 < g.Ez ? ez + 1 : 0, 1, cu, cv);
     wave_sync();
     // ---- y-map (lane (a=l0, c=l1), register b)
-    map_contrib<T, OP>(
+    map_contrib<T, OP, 3>(
         1,
         [&](int i, T (&Xr)[8]) {
 #pragma unroll
@@ -419,7 +260,7 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
     wave_sync();
     // ---- x-map (lane (b=l0, c=l1), register a): accumulate into the tile, keep face a = 7
     T R7[3];
-    map_contrib<T, OP>(
+    map_contrib<T, OP, 3>(
         0,
         [&](int i, T (&Xr)[8]) {
 #pragma unroll
@@ -548,22 +389,6 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   }
 }
 
-template <typename T>
-void fill_tab(int N, FastTab<T>* t) {
-  double xi[MAXP], w[MAXP], D[MAXP * MAXP];
-  gll_tables(N, xi, w, D);
-  for (int i = 0; i < 4; ++i)
-    for (int m = 0; m < 4; ++m) {
-      const double dim = D[i * 8 + m], dimr = D[i * 8 + 7 - m];
-      t->A[4 * i + m] = (T)(0.5 * (dim - dimr));
-      t->B[4 * i + m] = (T)(0.5 * (dim + dimr));
-    }
-  for (int q = 0; q < 8; ++q) {
-    t->w[q] = (T)w[q];
-    t->imq[q] = (T)(1.0 / ((q == 0 || q == 7) ? 2.0 * w[0] : w[q]));
-  }
-}
-
 FastArgs make_args(const ProbDev& hp, const ProbDev* dprob) {
   FastArgs g;
   g.Ex = hp.E[0];
@@ -632,9 +457,9 @@ int64_t fast3d_face_values(const ProbDev& hp) {
   return (int64_t)hp.batch * (hp.E[0] / WX) * hp.E[1] * 3 * hp.n[2] * FROWS;
 }
 
-size_t fast3d_table_bytes() { return sizeof(FastTab<double>) + sizeof(FastTab<float>); }
+size_t fast_table_bytes() { return sizeof(FastTab<double>) + sizeof(FastTab<float>); }
 
-void fast3d_fill_tables(int N, void* host) {
+void fast_fill_tables(int N, void* host) {
   fill_tab<double>(N, static_cast<FastTab<double>*>(host));
   fill_tab<float>(N, reinterpret_cast<FastTab<float>*>(static_cast<char*>(host) + sizeof(FastTab<double>)));
 }

@@ -186,7 +186,7 @@ struct OpSet {
   std::vector<Class> classes;
   int64_t total_vals = 0, total_nodes = 0, lvals = 0;
   DevBuf lvec;
-  bool fast = false;  // single 3-D problem handled by the tuned kernel
+  int fast = 0;  // one problem handled by a tuned kernel: 3 (kern_fast3d) or 2 (kern_fast2d)
   DevBuf face;
   DevBuf fast_tab;
   // persistent mixed-order launch (2-D sets): cost-sorted work list and per-order tables
@@ -204,9 +204,11 @@ struct OpSet {
   }
 
   hipError_t apply(int op, const void* u, const void* v, Coef in_scale, const Epi& epi, hipStream_t s) {
-    if (fast)
+    if (fast == 3)
       return launch_fast3d(hp[0], static_cast<const ProbDev*>(dprob.p), op, u, v, face.p, epi, in_scale, fast_tab.p,
                            dtype, s);
+    if (fast == 2)
+      return launch_fast2d(hp[0], static_cast<const ProbDev*>(dprob.p), op, u, v, epi, in_scale, fast_tab.p, dtype, s);
     if (persistent && nitems > 0) {
       hipError_t e = launch_persist2d(static_cast<const ProbDev*>(dprob.p), static_cast<const WorkItem*>(items.p), nitems,
                                       pgrid, op, dtype, dtype == SEM_F64 ? ptabs64.p : ptabs32.p, u, v, lvec.p,
@@ -239,7 +241,7 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     tmp[i].off = off[i];
   }
   os.total_vals = off[count];
-  os.fast = allow_fast && count == 1 && fast3d_supported(tmp[0]);
+  os.fast = !allow_fast || count != 1 ? 0 : fast3d_supported(tmp[0]) ? 3 : fast2d_supported(tmp[0]) ? 2 : 0;
   // order classes
   std::vector<int> idx(count);
   for (int i = 0; i < count; ++i) idx[i] = i;
@@ -319,11 +321,12 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
   os.total_nodes = nodes0;
   if (os.fast) {
     int rc;
-    std::vector<char> host(fast3d_table_bytes());
-    fast3d_fill_tables(descs[0].order, host.data());
+    std::vector<char> host(fast_table_bytes());
+    fast_fill_tables(descs[0].order, host.data());
     if ((rc = os.fast_tab.alloc(host.size()))) return rc;
     HIPCHK(hipMemcpy(os.fast_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
-    if ((rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts))) return rc;
+    if (os.fast == 3 && (rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts))) return rc;
+    if (os.fast == 2) HIPCHK(fast2d_prepare(os.dtype));
   }
   return os.finalize();
 }
@@ -1023,6 +1026,12 @@ int sem_query(sem_ctx c, int64_t* ndof, int64_t* nodes) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
   if (ndof) *ndof = c->ndof;
   if (nodes) *nodes = c->nodes;
+  return SEM_OK;
+}
+
+int sem_query_path(sem_ctx c, int32_t* path) {
+  if (!c || !path) return fail(SEM_ERR_ARG, "null argument");
+  *path = c->os.fast;
   return SEM_OK;
 }
 

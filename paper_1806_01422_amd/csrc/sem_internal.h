@@ -94,12 +94,16 @@ int persist2d_elems_per_item(int P);  // elements per work item for order P
 // Host GLL tables in long double (gll.cpp)
 void gll_tables(int N, double* xi, double* w, double* D);
 
-// Tuned 3-D path for order 7 (kern_fast3d.hip).  The epilogue output o1 must alias none of the
-// operator inputs nor x1/x2 (it temporarily holds partial sums).
+// Tuned order-7 paths (kern_fast3d.hip, kern_fast2d.hip) for one problem (any batch).  The
+// epilogue output o1 must alias neither operator input: other workgroups still read the input
+// nodes that a workgroup has finished.  Both paths take the same device table (fast_fill_tables).
 bool fast3d_supported(const ProbDev& hp);
 int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch
-size_t fast3d_table_bytes();
-void fast3d_fill_tables(int N, void* host);  // fills fast3d_table_bytes() bytes
+bool fast2d_supported(const ProbDev& hp);
+// lets the 2-D kernels of dtype use their workgroup LDS (more than the default dynamic limit)
+hipError_t fast2d_prepare(int dtype);
+size_t fast_table_bytes();
+void fast_fill_tables(int N, void* host);  // fills fast_table_bytes() bytes
 
 // Vector kernels (kern_blas.hip): out[j] = <X_j, w> for nv <= blas_max_vectors() vectors X_j at
 // stride ldx (FP64 accumulation, fixed order; partial holds blas_partial_bytes()), and
@@ -125,5 +129,7 @@ struct RevolveAct {
 int64_t revolve_plan(int64_t nsteps, int64_t snaps, std::vector<RevolveAct>& acts);
 hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
                          const Epi& epi, Coef in_scale, const void* dtables, int dtype, hipStream_t s);
+hipError_t launch_fast2d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, const Epi& epi,
+                         Coef in_scale, const void* dtables, int dtype, hipStream_t s);
 
 }  // namespace sem

@@ -76,6 +76,7 @@ _SIGS = {
     "sem_destroy": [_vp],
     "sem_set_stream": [_vp, _vp],
     "sem_query": [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "sem_query_path": [_vp, ctypes.POINTER(_i32)],
     "sem_node_coords": [_vp, _i32, ctypes.POINTER(_f64)],
     "sem_rhs": [_vp, _vp, _vp],
     "sem_jac_vec": [_vp, _vp, _vp, _vp],
@@ -175,6 +176,10 @@ class Context:
         self.ndof, self.nodes = ndof.value, nodes.value
         self.n = tuple(e * order for e in self.elems)
         self.shape = (batch, dim) + tuple(reversed(self.n))
+        path = _i32()
+        _call(lib().sem_query_path(self._h, ctypes.byref(path)))
+        # 0: element + summation kernels, 2 / 3: tuned order-7 2-D / 3-D kernel
+        self.path = path.value
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
