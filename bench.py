@@ -24,7 +24,7 @@ import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E datasheet peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fast3d_jact_32cube_n7.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1806_01422_amd", "csrc", "kern_fast3d.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_01422_amd", "csrc", f) for f in ("kern_fast3d.hip", "fast_common.h")]
 
 
 def measured_traffic():
@@ -33,7 +33,7 @@ def measured_traffic():
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        src = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRCS)).hexdigest()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("source_sha256:",
@@ -110,6 +110,37 @@ def gradient_c4(P, nsteps=wl.C4_STEPS, K=wl.C4_CKPT):
     grad()  # warm-up (graph capture, allocations)
     ms = event_time_ms(grad, 1)
     return cfg.batch / (ms / 1e3), ms
+
+
+def apply_2d(P):
+    """Single-apply throughput of F, J v and J^T w on the 2-D 64x64 N=7 FP64 mesh (nu = 1e-3), for one
+    field and for the 64 fields of the adjoint-gradient configuration; HBM fraction from the
+    algorithmic bytes (F, J v: 16 B/DOF and 24 B/DOF; J^T: 24 B/DOF)."""
+    cfg = wl.C2
+    out = {"workload": "2-D 64x64 N=7 FP64, nu=1e-3: one field, and 64 fields (the gradient batch)"}
+    for batch in (1, wl.C4.batch):
+        ctx = P.Context(2, cfg.N, cfg.E, cfg.L, cfg.nu, batch=batch)
+        xs = [ctx.node_coords(k) for k in range(2)]
+        u = np.stack([wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C4_IC_SEED0 + b) for b in range(batch)])
+        U = torch.from_numpy(u).cuda()
+        V = torch.from_numpy(wl.normal_field(ctx.shape, wl.C2_SEEDS["v"])).cuda()
+        W = torch.from_numpy(wl.normal_field(ctx.shape, wl.C2_SEEDS["w"])).cuda()
+        F, JV, JT = ctx.empty(), ctx.empty(), ctx.empty()
+        reps = 50
+        t_f = event_time_ms(lambda: ctx.rhs(U, F), reps)
+        t_jv = event_time_ms(lambda: ctx.jac_vec(U, V, JV), reps)
+        t_jt = event_time_ms(lambda: ctx.jact_vec(U, W, JT), reps)
+        dof = ctx.ndof * batch
+        out[f"fields_{batch}"] = {
+            "dof": dof, "kernel_path": ctx.path, "f_us": round(t_f * 1e3, 2), "jv_us": round(t_jv * 1e3, 2),
+            "jt_us": round(t_jt * 1e3, 2), "f_gdofs": round(dof / t_f / 1e6, 2), "jv_gdofs": round(dof / t_jv / 1e6, 2),
+            "jt_gdofs": round(dof / t_jt / 1e6, 2),
+            "f_hbm_frac": round(16.0 * dof / (t_f / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "jt_hbm_frac": round(24.0 * dof / (t_jt / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        ctx.close()
+        del U, V, W, F, JV, JT
+        torch.cuda.empty_cache()
+    return out
 
 
 def c5_sets(P):
@@ -287,6 +318,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated extra measurements to run (fp32, c2_apply, c4_adjoint, c5_batched, "
+                         "rk_adjoint, revolve, crank_nicolson, lmvm), or all")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain elementwise copy of one field (known bytes) for counter calibration")
     args = ap.parse_args()
@@ -361,7 +395,12 @@ def main():
     del U, V, W, F, JT, JV
     torch.cuda.empty_cache()
 
-    if not args.no_extras:
+    chosen = set(args.extras.split(","))
+
+    def want(name):
+        return not args.no_extras and ("all" in chosen or name in chosen)
+
+    if want("fp32"):
         c32 = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float32)
         U32, _, W32 = c3_inputs(c32, torch.float32)
         t_f32 = event_time_ms(lambda: c32.rhs(U32), reps)
@@ -377,20 +416,29 @@ def main():
         del U32, W32, U64, W64, f64, j64
         torch.cuda.empty_cache()
         log("fp32 done")
+    if want("c2_apply"):
+        out["c2_apply"] = apply_2d(P)
+        log("2-D apply done")
+    if want("c4_adjoint"):
         gps, ms = gradient_c4(P)
         out["c4_adjoint"] = {"gradients_per_s": round(gps, 3), "ms_per_batch_of_64": round(ms, 2),
                              "steps": wl.C4_STEPS, "ckpt_every": wl.C4_CKPT,
                              "workload": "2-D 64x64 N=7, 64 ICs, RK4 dt=2e-4, misfit gradient via autograd"}
         torch.cuda.empty_cache()
         log("c4 done")
+    if want("c5_batched"):
         out["c5_batched"] = gradient_c5(P)
         log("c5 done")
+    if want("rk_adjoint"):
         out["rk_adjoint"] = rk_adjoint_ratio(P)
         log("rk adjoint ratio done")
+    if want("revolve"):
         out["revolve"] = revolve_measure(P)
         log("revolve done")
+    if want("crank_nicolson"):
         out["crank_nicolson"] = cn_measure(P)
         log("crank-nicolson done")
+    if want("lmvm"):
         out["lmvm"] = lmvm_measure(P)
         log("lmvm done")
     if not args.no_cpu:

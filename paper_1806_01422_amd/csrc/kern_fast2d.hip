@@ -265,16 +265,26 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args g, const Fa
   }
 }
 
-Fast2Args make_args(const ProbDev& hp, const ProbDev* dprob) {
+// Segment length: about one workgroup per CU (256), so every workgroup starts in the first wave
+// of dispatch and the recomputed rows stay few (measured on 64 fields of 64 x 64 elements: 128,
+// 512, 1024 or 4096 workgroups are 5-50% slower for F, J v and J^T alike); at least 2 rows, so
+// the recomputed row costs at most half a segment.
+#ifndef SEM_FAST2D_TARGET_F
+#define SEM_FAST2D_TARGET_F 256
+#endif
+#ifndef SEM_FAST2D_TARGET_J
+#define SEM_FAST2D_TARGET_J 256
+#endif
+
+Fast2Args make_args(const ProbDev& hp, const ProbDev* dprob, int op) {
   Fast2Args g;
   g.Ex = hp.E[0];
   g.Ey = hp.E[1];
   g.nx = hp.n[0];
   g.ny = hp.n[1];
   g.nw = hp.E[0] / EW;
-  // segment length: enough workgroups to fill the chip (~512), at least 2 rows so the recomputed
-  // row costs at most half a segment
-  int64_t s = ((int64_t)hp.E[1] * hp.batch + 511) / 512;
+  const int64_t target = op == OP_RHS ? SEM_FAST2D_TARGET_F : SEM_FAST2D_TARGET_J;
+  int64_t s = ((int64_t)hp.E[1] * hp.batch + target - 1) / target;
   if (s < 2) s = 2;
   if (s > hp.E[1]) s = hp.E[1];
   g.S = (int)s;
@@ -311,7 +321,7 @@ hipError_t launch_ep(const Fast2Args& g, const FastTab<T>* tb, const T* u, const
 template <typename T>
 hipError_t run_fast2(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, const Epi& epi,
                      Coef in_scale, const void* dtab, hipStream_t s) {
-  const Fast2Args g = make_args(hp, dprob);
+  const Fast2Args g = make_args(hp, dprob, op);
   const auto* tb = static_cast<const FastTab<T>*>(dtab);
   const T* uu = static_cast<const T*>(u);
   const T* vv = static_cast<const T*>(v);
