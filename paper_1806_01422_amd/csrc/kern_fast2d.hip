@@ -177,15 +177,16 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args g, const Fa
           for (int b = 0; b < 8; ++b) r[i][b] = P[b];
         });
     // the y-map lines are no longer needed: move line 7 to line 0 and prefetch the next row's
-    // lines 1..7 (unconditionally: the last step loads the row after the segment); the second
-    // input follows after the x part, which keeps the registers in flight within budget
+    // lines 1..7 (unconditionally: the last step loads the row after the segment).  With a second
+    // input (J v, J^T) both prefetches wait until after the x part: in flight during it, they
+    // would push the kernel past its 256 registers.
     const int ey_next = ey + 1 < g.Ey ? ey + 1 : 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       cu[i][0] = cu[i][7];
       if constexpr (HASV) cv[i][0] = vlast[i];
     }
-    load_rows(ey_next, 1, true, false, cu, cv);
+    if constexpr (!HASV) load_rows(ey_next, 1, true, false, cu, cv);
     wave_sync();
     // ---- x-map (lane (b = l0, e), register a): x-direction part, written over component i of
     // the state tile once that component has been read
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args g, const Fa
 #pragma unroll
           for (int q = 0; q < 8; ++q) tU[i * TC + tix2(e, q, l0)] = P[q];
         });
-    if constexpr (HASV) load_rows(ey_next, 1, false, true, cu, cv);
+    if constexpr (HASV) load_rows(ey_next, 1, true, true, cu, cv);
     wave_sync();
     // ---- back to the y-map: element residual r = y part + x part
 #pragma unroll
@@ -267,8 +268,9 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args g, const Fa
 
 // Segment length: about one workgroup per CU (256), so every workgroup starts in the first wave
 // of dispatch and the recomputed rows stay few (measured on 64 fields of 64 x 64 elements: 128,
-// 512, 1024 or 4096 workgroups are 5-50% slower for F, J v and J^T alike); at least 2 rows, so
-// the recomputed row costs at most half a segment.
+// 512, 1024 or 4096 workgroups are 5-50% slower for F, J v and J^T alike).  Small launches go down
+// to one row per segment: recomputing every row is cheaper there than running half as many
+// workgroups (one 64 x 64 field: 10.7 instead of 14.3 us for F).
 #ifndef SEM_FAST2D_TARGET_F
 #define SEM_FAST2D_TARGET_F 256
 #endif
@@ -285,7 +287,7 @@ Fast2Args make_args(const ProbDev& hp, const ProbDev* dprob, int op) {
   g.nw = hp.E[0] / EW;
   const int64_t target = op == OP_RHS ? SEM_FAST2D_TARGET_F : SEM_FAST2D_TARGET_J;
   int64_t s = ((int64_t)hp.E[1] * hp.batch + target - 1) / target;
-  if (s < 2) s = 2;
+  if (s < 1) s = 1;
   if (s > hp.E[1]) s = hp.E[1];
   g.S = (int)s;
   g.nseg = (hp.E[1] + g.S - 1) / g.S;

@@ -12,7 +12,7 @@ import bench  # noqa: E402
 
 def test_traffic_matches_committed_summary():
     text = open(bench.TRAFFIC_FILE).read()
-    src = hashlib.sha256(open(bench.KERNEL_SRC, "rb").read()).hexdigest()
+    src = hashlib.sha256(b"".join(open(f, "rb").read() for f in bench.KERNEL_SRCS)).hexdigest()
     got = bench.measured_traffic()
     if f"source_sha256: {src}" in text:
         assert got is not None and got > 24.0 * 33718272  # at least the algorithmic bytes
@@ -21,10 +21,14 @@ def test_traffic_matches_committed_summary():
 
 
 def test_traffic_is_null_for_a_changed_kernel(tmp_path, monkeypatch):
-    changed = tmp_path / "kern.hip"
-    changed.write_bytes(open(bench.KERNEL_SRC, "rb").read() + b"\n// edited\n")
-    monkeypatch.setattr(bench, "KERNEL_SRC", str(changed))
-    assert bench.measured_traffic() is None
+    # an edit to either source the summary covers (the kernel or its shared header) voids it
+    for k in range(len(bench.KERNEL_SRCS)):
+        changed = tmp_path / f"src{k}"
+        changed.write_bytes(open(bench.KERNEL_SRCS[k], "rb").read() + b"\n// edited\n")
+        srcs = list(bench.KERNEL_SRCS)
+        srcs[k] = str(changed)
+        monkeypatch.setattr(bench, "KERNEL_SRCS", srcs)
+        assert bench.measured_traffic() is None
 
 
 def test_traffic_is_null_without_summary(tmp_path, monkeypatch):
