@@ -46,6 +46,21 @@ __device__ inline int find_node(const ProbDev* __restrict__ p, int n, int64_t it
   return lo;
 }
 
+// loc = b * per + r with per < 2^31 (checked at setup): 32-bit division unless loc itself needs 64
+// bits (batches beyond 2^31 values), which keeps the common path free of 64-bit division sequences
+__device__ __forceinline__ void split_item(int64_t loc, int64_t per, int& b, int& r) {
+  if (loc <= 0x7fffffff) {
+    const unsigned l = (unsigned)loc, p = (unsigned)per;
+    const unsigned q = l / p;
+    b = (int)q;
+    r = (int)(l - q * p);
+  } else {
+    const int64_t q = loc / per;
+    b = (int)q;
+    r = (int)(loc - q * per);
+  }
+}
+
 // (D_j S)(q) = sum_m D[q_j][m] S(q; q_j <- m)   (unscaled; caller multiplies by 2/h_j)
 template <typename T, int P>
 __device__ inline T contract(const T* __restrict__ s, const T* __restrict__ D, int row, int base, int st) {
@@ -96,14 +111,17 @@ __device__ __forceinline__ void elem_body(int tid, const ProbDev* __restrict__ p
   int64_t lbase = 0;
   if (valid) {
     const int N = pr->N;
-    const int64_t b = loc / pr->nelem;
-    const int64_t e = loc - b * pr->nelem;
+    int b, e;
+    split_item(loc, pr->nelem, b, e);
     int ed[3];
-    ed[0] = (int)(e % pr->E[0]);
-    const int64_t e1 = e / pr->E[0];
-    ed[1] = (int)(e1 % pr->E[1]);
-    ed[2] = (int)(e1 / pr->E[1]);
-    int64_t g = 0, stride = 1;
+    {
+      const unsigned E0 = (unsigned)pr->E[0], E1 = (unsigned)pr->E[1];
+      const unsigned e1 = (unsigned)e / E0;
+      ed[0] = (int)((unsigned)e - e1 * E0);
+      ed[1] = (int)(e1 % E1);
+      ed[2] = (int)(e1 / E1);
+    }
+    int g = 0, stride = 1;
     double omd = 1.0, mass = 1.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -116,7 +134,7 @@ __device__ __forceinline__ void elem_body(int tid, const ProbDev* __restrict__ p
     }
     om = (T)omd;
     nu = (T)pr->nu;
-    const int64_t base = pr->off + b * C * pr->nodes + g;
+    const int64_t base = pr->off + (int64_t)b * C * pr->nodes + g;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       U[c] = u[base + c * pr->nodes];
@@ -217,8 +235,18 @@ __global__ __launch_bounds__(EPB* ipow(P, DIM)) void elem_kernel(const ProbDev* 
   const int tid = threadIdx.x;
   const int64_t item = (int64_t)blockIdx.x * EPB + tid / NL;
   const bool valid = item < nitems;
-  const ProbDev* pr = probs + (valid ? find_item(probs, nprobs, item) : 0);
-  elem_body<T, DIM, P, OP, EPB>(tid, pr, valid ? item - pr->item0 : -1, tab->D, sD, sIn, sT, u, v, L, in_scale);
+  // a workgroup inside one problem (the common case) reads that problem's entry through
+  // workgroup-uniform (scalar) loads
+  const int64_t first = (int64_t)blockIdx.x * EPB;
+  const int64_t last = first + EPB <= nitems ? first + EPB - 1 : nitems - 1;
+  const int pf = find_item(probs, nprobs, first);
+  if (pf == find_item(probs, nprobs, last)) {
+    const ProbDev* pr = probs + pf;
+    elem_body<T, DIM, P, OP, EPB>(tid, pr, valid ? item - pr->item0 : -1, tab->D, sD, sIn, sT, u, v, L, in_scale);
+  } else {
+    const ProbDev* pr = probs + (valid ? find_item(probs, nprobs, item) : 0);
+    elem_body<T, DIM, P, OP, EPB>(tid, pr, valid ? item - pr->item0 : -1, tab->D, sD, sIn, sT, u, v, L, in_scale);
+  }
 }
 
 // Persistent element kernel over a 2-D problem set of mixed orders: workgroup b processes work
@@ -263,22 +291,19 @@ __global__ __launch_bounds__(NT) void persist2d_kernel(const ProbDev* __restrict
 }
 
 template <typename T, int DIM, bool DIV>
-__global__ __launch_bounds__(256) void dss_kernel(const ProbDev* __restrict__ probs, int nprobs, int64_t nitems,
-                                                  const T* __restrict__ L, Epi epi) {
-  const int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (item >= nitems) return;
-  const ProbDev* pr = probs + find_node(probs, nprobs, item);
+__device__ __forceinline__ void dss_node(const ProbDev* __restrict__ pr, int64_t item, const T* __restrict__ L,
+                                         const Epi& epi) {
   const int N = pr->N, P = pr->P;
-  const int64_t loc = item - pr->node0;
-  const int64_t b = loc / pr->nodes;
-  const int64_t g = loc - b * pr->nodes;
+  int b, g;
+  split_item(item - pr->node0, pr->nodes, b, g);
   int gd[3] = {0, 0, 0};
   {
-    int64_t t = g;
+    unsigned t = (unsigned)g;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-      gd[k] = (int)(t % pr->n[k]);
-      t /= pr->n[k];
+      const unsigned nk = (unsigned)pr->n[k], q = t / nk;
+      gd[k] = (int)(t - q * nk);
+      t = q;
     }
   }
   // contributing (element, local index) pairs per direction: (g/N, g%N) and, on an element
@@ -299,21 +324,21 @@ __global__ __launch_bounds__(256) void dss_kernel(const ProbDev* __restrict__ pr
     }
   }
   const int NL = (DIM == 1) ? P : (DIM == 2) ? P * P : P * P * P;
-  const int64_t lb = pr->loff + b * pr->nelem * DIM * (int64_t)NL;
+  const int64_t lb = pr->loff + (int64_t)b * pr->nelem * DIM * (int64_t)NL;
   const double dt = pr->dt;
   const T b1 = (T)(epi.b1.c0 + epi.b1.cdt * dt), a1 = (T)(epi.a1.c0 + epi.a1.cdt * dt);
   const T b2 = (T)(epi.b2.c0 + epi.b2.cdt * dt), a2 = (T)(epi.a2.c0 + epi.a2.cdt * dt);
   const T c1 = (T)(epi.c1.c0 + epi.c1.cdt * dt), c2 = (T)(epi.c2.c0 + epi.c2.cdt * dt);
-  const int64_t ob = pr->off + b * DIM * pr->nodes + g;
+  const int64_t ob = pr->off + (int64_t)b * DIM * pr->nodes + g;
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
     T s = 0;
     for (int x = 0; x < ne[0]; ++x)
       for (int y = 0; y < ne[1]; ++y)
         for (int z = 0; z < ne[2]; ++z) {
-          const int64_t e = ee[0][x] + (int64_t)pr->E[0] * (ee[1][y] + (int64_t)pr->E[1] * ee[2][z]);
+          const int e = ee[0][x] + pr->E[0] * (ee[1][y] + pr->E[1] * ee[2][z]);  // < nelem < 2^31
           const int q = qq[0][x] + P * (qq[1][y] + P * qq[2][z]);
-          s += L[lb + (e * DIM + c) * NL + q];
+          s += L[lb + ((int64_t)e * DIM + c) * NL + q];
         }
     if (DIV) s = s / (T)mass;
     const int64_t o = ob + c * pr->nodes;
@@ -323,6 +348,22 @@ __global__ __launch_bounds__(256) void dss_kernel(const ProbDev* __restrict__ pr
     if (epi.o2) static_cast<T*>(epi.o2)[o] = b2 * s + a2 * v2 + c2 * v1;
     static_cast<T*>(epi.o1)[o] = b1 * s + a1 * v1 + c1 * v2;
   }
+}
+
+template <typename T, int DIM, bool DIV>
+__global__ __launch_bounds__(256) void dss_kernel(const ProbDev* __restrict__ probs, int nprobs, int64_t nitems,
+                                                  const T* __restrict__ L, Epi epi) {
+  const int64_t first = (int64_t)blockIdx.x * 256;
+  const int64_t item = first + threadIdx.x;
+  const int64_t last = first + 256 <= nitems ? first + 255 : nitems - 1;
+  // a workgroup inside one problem (the common case) reads its entry through uniform loads
+  const int pf = find_node(probs, nprobs, first);
+  const bool uniform = pf == find_node(probs, nprobs, last);
+  if (item >= nitems) return;
+  if (uniform)
+    dss_node<T, DIM, DIV>(probs + pf, item, L, epi);
+  else
+    dss_node<T, DIM, DIV>(probs + find_node(probs, nprobs, item), item, L, epi);
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -106,6 +106,8 @@ int validate_desc(const sem_desc* d) {
     if ((int64_t)d->elems[k] * d->order > (int64_t)1 << 30) return fail(SEM_ERR_ARG, "mesh too large");
     nodes *= (int64_t)d->elems[k] * d->order;
   }
+  // kernel index arithmetic is 32-bit within one batch member
+  if (nodes >= ((int64_t)1 << 31)) return fail(SEM_ERR_ARG, "mesh too large: %lld nodes per component", (long long)nodes);
   if (nodes * d->dim * (int64_t)d->batch > ((int64_t)1 << 40)) return fail(SEM_ERR_ARG, "field too large");
   return SEM_OK;
 }
