@@ -108,8 +108,12 @@ int sem_rk4_forward(sem_ctx ctx, void* u, double dt, int32_t nsteps, int32_t ckp
    for the classical RK4 tableau): on entry lam holds lambda_N = dPhi/du(T); on exit lambda_0 =
    dPhi/du_0.  Uses the checkpoints written by sem_rk4_forward with the same dt, nsteps and
    ckpt_every, and recomputes each segment of K states into work (Sec. 5.3).  work: device buffer
-   of at least sem_workspace_bytes(ctx, ckpt_every) bytes.  Per step the stage states are
-   recomputed (3 F) and four J^T products are applied. */
+   of at least sem_workspace_bytes(ctx, ckpt_every) bytes.  Stage states: by default, states of
+   4M values or more have the segment recompute store every step's stage states in work (4 F per
+   step, as an adjoint with stored stages), and each adjoint step then only applies the four J^T
+   products; smaller states keep one state per step and recompute the stage states in each
+   adjoint step (3 F more per step, but every step is one captured graph).  Both give the same
+   values; sem_set_adjoint_stages overrides the choice. */
 int sem_rk4_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every,
                     void* lam, void* work);
 /* The same two calls for any sem_scheme: the stage updates of every scheme are fused into the
@@ -214,8 +218,16 @@ int sem_lmvm_workspace_bytes(sem_ctx ctx, int32_t scheme, int32_t nsteps, int32_
 int sem_lmvm_initial_condition(sem_ctx ctx, int32_t scheme, void* u0, const void* target, double dt, int32_t nsteps,
                                int32_t ckpt_every, const sem_lmvm_opts* opts, void* work, double* history,
                                sem_lmvm_stats* stats);
-/* Bytes of caller work buffer needed by sem_rk4_adjoint / sem_rk_adjoint for a given ckpt_every. */
+/* Bytes of caller work buffer needed by sem_rk4_adjoint / sem_rk_adjoint for a given ckpt_every:
+   ckpt_every states, or 4 ckpt_every states when stage states are stored (query again after
+   sem_set_adjoint_stages). */
 int sem_workspace_bytes(sem_ctx ctx, int32_t ckpt_every, int64_t* bytes);
+/* How the RK adjoints obtain the stage states of a step (host only): SEM_ADJ_AUTO (default:
+   stored for states of 4M values or more), SEM_ADJ_STORE (always stored: the segment recompute
+   writes them to work), SEM_ADJ_RECOMPUTE (never: each adjoint step recomputes them, 2 F for
+   RK-3 and 3 F for RK4).  Other values are SEM_ERR_ARG. */
+typedef enum { SEM_ADJ_AUTO = 0, SEM_ADJ_STORE = 1, SEM_ADJ_RECOMPUTE = 2 } sem_adj_stages;
+int sem_set_adjoint_stages(sem_ctx ctx, int32_t mode);
 /* Enable (1) or disable (0, default) the non-finite check at the end of sem_rk4_forward (one
    host synchronisation per call). */
 int sem_set_check_finite(sem_ctx ctx, int32_t on);
@@ -252,6 +264,8 @@ int sem_batch_rk_forward(sem_batch b, int32_t scheme, void* u, int32_t nsteps, i
 int sem_batch_rk_adjoint(sem_batch b, int32_t scheme, const void* ckpt, int32_t nsteps, int32_t ckpt_every,
                          void* lam, void* work);
 int sem_batch_workspace_bytes(sem_batch b, int32_t ckpt_every, int64_t* bytes);
+/* sem_set_adjoint_stages for a batch (the state is the whole packed set). */
+int sem_batch_set_adjoint_stages(sem_batch b, int32_t mode);
 /* Launch shape of the element stage.  persistent = 1: one persistent launch over all problems
    (2-D sets of more than one problem) with `param` workgroups walking a cost-sorted work list;
    persistent = 0: one launch per order class with `param` elements per workgroup (0 = default;

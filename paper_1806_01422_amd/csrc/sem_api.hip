@@ -345,6 +345,20 @@ struct Integrator {
   hipStream_t cap = nullptr;
   hipGraphExec_t gstep[NSCHEME] = {}, gadj[NSCHEME] = {};
   DevBuf dts;  // per-problem dt table for the batch
+  // Adjoint with uniform checkpoints: the segment recompute writes every step's stage states to
+  // the work buffer and the adjoint steps read them (as an adjoint with stored stages does, Sec.
+  // 4.1), instead of recomputing them in each adjoint step.  Those launches address a different
+  // work slot every step, so they run uncaptured; for small states, where launch overhead would
+  // dominate, the captured recompute-in-step graphs run instead.  Both give the same values.
+  int adj_mode = SEM_ADJ_AUTO;
+  static constexpr int64_t STORE_MIN_VALUES = (int64_t)1 << 22;  // auto: stored stages from 4M values
+  static constexpr int MAX_STAGE_STATES = 4;                       // u, U2, U3, U4 (RK4)
+  static int stage_states(int scheme) { return scheme == SEM_RK3 ? 3 : 4; }
+  bool stores_stages() const {
+    return adj_mode == SEM_ADJ_STORE || (adj_mode == SEM_ADJ_AUTO && n >= STORE_MIN_VALUES);
+  }
+  // states the caller's adjoint work buffer holds for ckpt_every K
+  int64_t work_states(int32_t K) const { return (int64_t)K * (stores_stages() ? MAX_STAGE_STATES : 1); }
 
   ~Integrator() {
     reset_graphs();
@@ -395,12 +409,19 @@ struct Integrator {
     if ((e = os->apply(OP_RHS, b(USTATE), nullptr, one, ep, s))) return e;
     ep = Epi{b(A3), b(USTATE), {3, 0}, {0, 2.0}, nullptr, b(A2), zero, zero, {-2, 0}, zero};
     if ((e = os->apply(OP_RHS, b(A2), nullptr, one, ep, s))) return e;
-    ep = Epi{b(T1), b(LAMB), {0, 2.0 / 3}, {0, 2.0}, b(LACC), b(LAMB), one, one};
-    if ((e = os->apply(OP_JACT, b(A3), b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
+    const void* st[2] = {b(A2), b(A3)};
+    return enqueue_adjoint_jt_rk3(s, b(USTATE), st);
+  }
+  // the J^T part of the RK-3 adjoint step from u and its stage states st = {U2, U3}
+  hipError_t enqueue_adjoint_jt_rk3(hipStream_t s, const void* u, const void* const* st) {
+    hipError_t e;
+    const Coef one{1, 0}, zero{0, 0};
+    Epi ep{b(T1), b(LAMB), {0, 2.0 / 3}, {0, 2.0}, b(LACC), b(LAMB), one, one};
+    if ((e = os->apply(OP_JACT, st[1], b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
     ep = Epi{b(T2), b(LAMB), {0, 7.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one, {0, -1.0}, zero};
-    if ((e = os->apply(OP_JACT, b(A2), b(T1), one, ep, s))) return e;
+    if ((e = os->apply(OP_JACT, st[0], b(T1), one, ep, s))) return e;
     ep = Epi{b(LAMB), b(LACC), one, one, nullptr, nullptr, zero, zero};
-    return os->apply(OP_JACT, b(USTATE), b(T2), one, ep, s);
+    return os->apply(OP_JACT, u, b(T2), one, ep, s);
   }
 
   // one RK4 step on STATE (stage updates fused into the summation epilogues)
@@ -434,14 +455,51 @@ struct Integrator {
     if ((e = os->apply(OP_RHS, b(A2), nullptr, one, ep, s))) return e;
     ep = Epi{b(A4), b(USTATE), one, {0, 1.0}, nullptr, nullptr, zero, zero};
     if ((e = os->apply(OP_RHS, b(A3), nullptr, one, ep, s))) return e;
-    ep = Epi{b(T1), b(LAMB), {0, 1.0 / 3}, {0, 1.0}, b(LACC), b(LAMB), one, one};
-    if ((e = os->apply(OP_JACT, b(A4), b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
+    const void* st[3] = {b(A2), b(A3), b(A4)};
+    return enqueue_adjoint_jt_rk4(s, b(USTATE), st);
+  }
+  // the J^T part of the RK4 adjoint step from u and its stage states st = {U2, U3, U4}
+  hipError_t enqueue_adjoint_jt_rk4(hipStream_t s, const void* u, const void* const* st) {
+    hipError_t e;
+    const Coef one{1, 0}, zero{0, 0};
+    Epi ep{b(T1), b(LAMB), {0, 1.0 / 3}, {0, 1.0}, b(LACC), b(LAMB), one, one};
+    if ((e = os->apply(OP_JACT, st[2], b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
     ep = Epi{b(T2), b(LAMB), {0, 1.0 / 3}, {0, 0.5}, b(LACC), b(LACC), one, one};
-    if ((e = os->apply(OP_JACT, b(A3), b(T1), one, ep, s))) return e;
+    if ((e = os->apply(OP_JACT, st[1], b(T1), one, ep, s))) return e;
     ep = Epi{b(T1), b(LAMB), {0, 1.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one};
-    if ((e = os->apply(OP_JACT, b(A2), b(T2), one, ep, s))) return e;
+    if ((e = os->apply(OP_JACT, st[0], b(T2), one, ep, s))) return e;
     ep = Epi{b(LAMB), b(LACC), one, one, nullptr, nullptr, zero, zero};
-    return os->apply(OP_JACT, b(USTATE), b(T1), one, ep, s);
+    return os->apply(OP_JACT, u, b(T1), one, ep, s);
+  }
+
+  // One step from u with its stage states written to st (RK4: U2, U3, U4; RK-3: U2, U3) and the
+  // new state to unext: the same launches and coefficients as the captured step, so the states
+  // are the same values.  With unext null (the last step of a segment) only the stage states are
+  // formed, without the accumulator, as in the adjoint step's own recompute.
+  hipError_t enqueue_step_stages(hipStream_t s, int scheme, const void* u, void* const* st, void* unext) {
+    hipError_t e;
+    const Coef one{1, 0}, zero{0, 0};
+    void* acc = unext ? b(ACC) : nullptr;
+    Epi ep{};
+    if (scheme == SEM_RK3) {
+      ep = Epi{st[0], u, one, {0, 0.5}, nullptr, nullptr, zero, zero};
+      if ((e = os->apply(OP_RHS, u, nullptr, one, ep, s))) return e;
+      ep = unext ? Epi{st[1], u, {3, 0}, {0, 2.0}, acc, st[0], {1.0 / 3, 0}, {0, 2.0 / 3}, {-2, 0}, {2.0 / 3, 0}}
+                 : Epi{st[1], u, {3, 0}, {0, 2.0}, nullptr, st[0], zero, zero, {-2, 0}, zero};
+      if ((e = os->apply(OP_RHS, st[0], nullptr, one, ep, s))) return e;
+      if (!unext) return hipSuccess;
+      ep = Epi{unext, b(ACC), one, {0, 1.0 / 6}, nullptr, nullptr, zero, zero};
+      return os->apply(OP_RHS, st[1], nullptr, one, ep, s);
+    }
+    ep = Epi{st[0], u, one, {0, 0.5}, acc, unext ? u : nullptr, one, {0, 1.0 / 6}};
+    if ((e = os->apply(OP_RHS, u, nullptr, one, ep, s))) return e;
+    ep = Epi{st[1], u, one, {0, 0.5}, acc, acc, one, {0, 1.0 / 3}};
+    if ((e = os->apply(OP_RHS, st[0], nullptr, one, ep, s))) return e;
+    ep = Epi{st[2], u, one, {0, 1.0}, acc, acc, one, {0, 1.0 / 3}};
+    if ((e = os->apply(OP_RHS, st[1], nullptr, one, ep, s))) return e;
+    if (!unext) return hipSuccess;
+    ep = Epi{unext, b(ACC), one, {0, 1.0 / 6}, nullptr, nullptr, zero, zero};
+    return os->apply(OP_RHS, st[2], nullptr, one, ep, s);
   }
 
   int alloc_buffers() {
@@ -509,6 +567,26 @@ struct Integrator {
     const size_t bytes = n * ts;
     char* wk = static_cast<char*>(work);
     HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
+    if (stores_stages()) {
+      // work: [K][stage_states][n]; slot (k, 0) holds u_k, slots (k, 1..) its stage states
+      const int ns = stage_states(scheme);
+      auto slot = [&](int k, int j) -> void* { return wk + ((size_t)k * ns + j) * bytes; };
+      for (int sg = nsteps / K - 1; sg >= 0; --sg) {
+        HIPCHK(hipMemcpyAsync(slot(0, 0), static_cast<const char*>(ckpt) + (size_t)sg * bytes, bytes,
+                              hipMemcpyDeviceToDevice, s));
+        for (int k = 0; k < K; ++k) {
+          void* st[3] = {slot(k, 1), slot(k, 2), ns > 3 ? slot(k, 3) : nullptr};
+          HIPCHK(enqueue_step_stages(s, scheme, slot(k, 0), st, k + 1 < K ? slot(k + 1, 0) : nullptr));
+        }
+        for (int k = K - 1; k >= 0; --k) {
+          const void* st[3] = {slot(k, 1), slot(k, 2), ns > 3 ? slot(k, 3) : nullptr};
+          HIPCHK(scheme == SEM_RK3 ? enqueue_adjoint_jt_rk3(s, slot(k, 0), st)
+                                   : enqueue_adjoint_jt_rk4(s, slot(k, 0), st));
+        }
+      }
+      HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
+      return SEM_OK;
+    }
     for (int sg = nsteps / K - 1; sg >= 0; --sg) {
       HIPCHK(hipMemcpyAsync(b(STATE), static_cast<const char*>(ckpt) + (size_t)sg * bytes, bytes,
                             hipMemcpyDeviceToDevice, s));
@@ -1112,7 +1190,15 @@ int sem_rk_forward(sem_ctx c, int32_t scheme, void* u, double dt, int32_t nsteps
 int sem_workspace_bytes(sem_ctx c, int32_t K, int64_t* bytes) {
   if (!c || !bytes) return fail(SEM_ERR_ARG, "null argument");
   if (K < 1) return fail(SEM_ERR_ARG, "ckpt_every %d < 1", K);
-  *bytes = (int64_t)K * c->integ.n * (int64_t)c->os.ts;
+  *bytes = c->integ.work_states(K) * c->integ.n * (int64_t)c->os.ts;
+  return SEM_OK;
+}
+
+int sem_set_adjoint_stages(sem_ctx c, int32_t mode) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (mode != SEM_ADJ_AUTO && mode != SEM_ADJ_STORE && mode != SEM_ADJ_RECOMPUTE)
+    return fail(SEM_ERR_ARG, "adjoint stage mode %d", mode);
+  c->integ.adj_mode = mode;
   return SEM_OK;
 }
 
@@ -1199,8 +1285,8 @@ static sem_lmvm_opts lmvm_defaults(const sem_lmvm_opts* o) {
 
 // states of the LMVM work buffer: 6 iterate/scratch vectors, 2 m pairs, the residual, the checkpoints and
 // the adjoint work of the scheme
-static int64_t lmvm_states(int32_t scheme, int32_t nsteps, int32_t K, const sem_lmvm_opts& o) {
-  const int64_t adj = scheme == SEM_CN ? (int64_t)K + 1 + 30 + 2 : (int64_t)K;
+static int64_t lmvm_states(const Integrator& in, int32_t scheme, int32_t nsteps, int32_t K, const sem_lmvm_opts& o) {
+  const int64_t adj = scheme == SEM_CN ? (int64_t)K + 1 + 30 + 2 : in.work_states(K);
   return 6 + 2 * (int64_t)o.memory + 1 + nsteps / K + adj;
 }
 
@@ -1210,7 +1296,7 @@ int sem_lmvm_workspace_bytes(sem_ctx c, int32_t scheme, int32_t nsteps, int32_t 
   if (scheme != SEM_RK4 && scheme != SEM_RK3 && scheme != SEM_CN) return fail(SEM_ERR_ARG, "unknown scheme %d", scheme);
   if (int rc = check_steps(1.0, nsteps, K, true)) return rc;
   const sem_lmvm_opts o = lmvm_defaults(opts);
-  *bytes = lmvm_states(scheme, nsteps, K, o) * c->integ.n * (int64_t)c->os.ts;
+  *bytes = lmvm_states(c->integ, scheme, nsteps, K, o) * c->integ.n * (int64_t)c->os.ts;
   return SEM_OK;
 }
 
@@ -1403,7 +1489,15 @@ int sem_batch_jact_vec(sem_batch b, const void* u, const void* w, void* jtw) {
 int sem_batch_workspace_bytes(sem_batch b, int32_t K, int64_t* bytes) {
   if (!b || !bytes) return fail(SEM_ERR_ARG, "null argument");
   if (K < 1) return fail(SEM_ERR_ARG, "ckpt_every %d < 1", K);
-  *bytes = (int64_t)K * b->integ.n * (int64_t)b->os.ts;
+  *bytes = b->integ.work_states(K) * b->integ.n * (int64_t)b->os.ts;
+  return SEM_OK;
+}
+
+int sem_batch_set_adjoint_stages(sem_batch b, int32_t mode) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (mode != SEM_ADJ_AUTO && mode != SEM_ADJ_STORE && mode != SEM_ADJ_RECOMPUTE)
+    return fail(SEM_ERR_ARG, "adjoint stage mode %d", mode);
+  b->integ.adj_mode = mode;
   return SEM_OK;
 }
 

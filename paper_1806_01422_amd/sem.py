@@ -71,6 +71,7 @@ class SemDesc(ctypes.Structure):
 _lib = None
 _vp = ctypes.c_void_p
 _i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+ADJOINT_STAGES = {"auto": 0, "store": 1, "recompute": 2}  # sem_adj_stages
 _SIGS = {
     "sem_setup": [ctypes.POINTER(SemDesc), _vp, ctypes.POINTER(_vp)],
     "sem_destroy": [_vp],
@@ -84,6 +85,7 @@ _SIGS = {
     "sem_rk4_forward": [_vp, _vp, _f64, _i32, _i32, _vp],
     "sem_rk4_adjoint": [_vp, _vp, _f64, _i32, _i32, _vp, _vp],
     "sem_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
+    "sem_set_adjoint_stages": [_vp, _i32],
     "sem_set_check_finite": [_vp, _i32],
     "sem_last_error": [],
     "sem_batch_setup": [ctypes.POINTER(SemDesc), ctypes.POINTER(_f64), _i32, _vp, ctypes.POINTER(_vp)],
@@ -108,6 +110,7 @@ _SIGS = {
     "sem_batch_rk_forward": [_vp, _i32, _vp, _i32, _i32, _vp],
     "sem_batch_rk_adjoint": [_vp, _i32, _vp, _i32, _i32, _vp, _vp],
     "sem_batch_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
+    "sem_batch_set_adjoint_stages": [_vp, _i32],
     "sem_batch_configure": [_vp, _i32, _i32],
     "sem_batch_autotune": [_vp, ctypes.POINTER(_f64)],
 }
@@ -254,6 +257,10 @@ class Context:
         b = _i64()
         _call(lib().sem_workspace_bytes(self._h, int(ckpt_every), ctypes.byref(b)))
         return b.value
+
+    def set_adjoint_stages(self, mode):
+        """How the RK adjoints obtain stage states: "auto", "store" or "recompute"."""
+        _call(lib().sem_set_adjoint_stages(self._h, ADJOINT_STAGES[mode]))
 
     def _adjoint_args(self, ckpt, nsteps, ckpt_every, lamT, work):
         self._chk(lamT, "lamT")
@@ -532,6 +539,10 @@ class Batch:
         _call(lib().sem_batch_rk4_forward(self._h, _ptr(u), int(nsteps), int(ckpt_every),
                                           _ptr(ck) if ck is not None else None))
         return u, ck
+
+    def set_adjoint_stages(self, mode):
+        """How the RK adjoints obtain stage states: "auto", "store" or "recompute"."""
+        _call(lib().sem_batch_set_adjoint_stages(self._h, ADJOINT_STAGES[mode]))
 
     def _work(self, ckpt_every, work):
         if work is None:

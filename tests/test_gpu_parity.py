@@ -267,6 +267,29 @@ def test_rk4_forward_adjoint(P, dim, N, E, batch):
     assert rel(lam, lam_ref) < TOL_TRAJ
 
 
+@pytest.mark.parametrize("scheme", ["rk4", "rk3"])
+@pytest.mark.parametrize("dim,N,E,batch", [(2, 7, [8, 3], 2), (3, 7, [4, 2, 3], 1), (2, 5, [4, 3], 2), (1, 8, [16], 1)])
+def test_adjoint_stage_modes(P, scheme, dim, N, E, batch):
+    # stage states stored by the segment recompute (uncaptured launches) or recomputed in every
+    # adjoint step (captured graphs): the same launches on the same states, so the same values
+    note(f"adjoint stage modes {scheme} dim={dim} N={N} E={E} batch={batch}")
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    u, _, w = fields(m, 37)
+    dt, n, K = (2e-3 if dim > 1 else 2e-4), 12, 4
+    uT, ck = c.rk_forward(gpu(u), dt, n, K, scheme=scheme)
+    c.set_adjoint_stages("recompute")
+    wr = c.workspace_bytes(K)
+    lam_r = c.rk_adjoint(ck, dt, n, K, gpu(w), scheme=scheme)
+    c.set_adjoint_stages("store")
+    assert c.workspace_bytes(K) == 4 * wr
+    lam_s = c.rk_adjoint(ck, dt, n, K, gpu(w), scheme=scheme)
+    assert torch.equal(lam_s, lam_r)
+    ref, ckr = m.erk_forward(scheme, u, dt, n, K)
+    assert rel(lam_s, m.erk_adjoint(scheme, ckr, dt, n, K, w)) < TOL_TRAJ
+    c.set_adjoint_stages("auto")
+    assert c.workspace_bytes(K) == wr  # these states are small: recompute by default
+
+
 def test_c4_shape_batch_gradient(P):
     # the 64-IC 2-D configuration at full mesh size; a 50-step horizon keeps the oracle side short.
     cfg = wl.C4
@@ -337,6 +360,9 @@ def test_batch_trajectory_gradient(P):
     n, K = 12, 4
     uT, ck = B.rk4_forward(u, n, K)
     lam0 = B.rk4_adjoint(ck, n, K, lam)
+    B.set_adjoint_stages("store")  # stored stage states give the same values
+    assert torch.equal(B.rk4_adjoint(ck, n, K, lam), lam0)
+    B.set_adjoint_stages("auto")
     for i, s in enumerate(specs):
         if s["elems"][0] > 16:
             continue  # keep the oracle side short
