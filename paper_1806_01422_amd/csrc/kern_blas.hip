@@ -1,5 +1,6 @@
 // Vector kernels for the Newton-Krylov solvers: dot products of one vector with several others
-// (deterministic two-stage reduction in FP64) and combinations y = a y + sum_j c_j x_j with the
+// (deterministic two-stage reduction in FP64: fixed-order partial sums per block, then a fixed
+// tree per vector) and combinations y = a y + sum_j c_j x_j with the
 // coefficients read from device memory, so a Gram-Schmidt step needs no host round trip between
 // its projection and its update.
 #include "sem_internal.h"
@@ -7,48 +8,60 @@
 namespace sem {
 namespace {
 
-constexpr int BT = 256;       // threads per block
-constexpr int MAXV = 40;      // most vectors in one multi-dot or combination
-constexpr int DOT_BLOCKS = 512;
+constexpr int BT = 256;          // threads per block
+constexpr int MAXV = 40;         // most vectors in one multi-dot or combination
+constexpr int CH = 8;            // vectors per multi-dot chunk (blockIdx.y)
+constexpr int DOT_BLOCKS = 2048; // partial sums per vector
 
-// partial[b][j] = sum over this block's strided range of x_j[i] * w[i]
+// partial[b][j] = sum over block b's strided range of x_j[i] * w[i], for the chunk of vectors
+// j0 = CH * blockIdx.y .. j0 + CH - 1 (fixed order within the block: per thread, then per wavefront
+// by shuffles, then over the wavefronts)
 template <typename T>
 __global__ __launch_bounds__(BT) void multidot_partial(const T* __restrict__ X, int64_t ldx, int nv,
                                                        const T* __restrict__ w, int64_t n,
                                                        double* __restrict__ partial) {
-  __shared__ double red[BT / 64][MAXV];
-  double acc[MAXV];
+  __shared__ double red[BT / 64][CH];
+  const int j0 = CH * blockIdx.y;
+  const int nc = nv - j0 < CH ? nv - j0 : CH;
+  double acc[CH];
 #pragma unroll
-  for (int j = 0; j < MAXV; ++j) acc[j] = 0.0;
+  for (int j = 0; j < CH; ++j) acc[j] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
     const double wi = (double)w[i];
 #pragma unroll
-    for (int j = 0; j < MAXV; ++j)
-      if (j < nv) acc[j] += (double)X[j * ldx + i] * wi;
+    for (int j = 0; j < CH; ++j)
+      if (j < nc) acc[j] += (double)X[(j0 + j) * ldx + i] * wi;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < MAXV; ++j) {
-    if (j >= nv) break;
+  for (int j = 0; j < CH; ++j) {
     double v = acc[j];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (lane == 0) red[wave][j] = v;
   }
   __syncthreads();
-  if (threadIdx.x < nv) {
+  if (threadIdx.x < nc) {
     double s = 0.0;
     for (int k = 0; k < BT / 64; ++k) s += red[k][threadIdx.x];
-    partial[(int64_t)blockIdx.x * MAXV + threadIdx.x] = s;
+    partial[(int64_t)blockIdx.x * MAXV + j0 + threadIdx.x] = s;
   }
 }
 
-// out[j] = sum over blocks of partial[b][j] (fixed order)
-__global__ void multidot_final(const double* __restrict__ partial, int nblocks, int nv, double* __restrict__ out) {
-  const int j = threadIdx.x;
-  if (j >= nv) return;
+// out[j] = sum over blocks of partial[b][j]: block j, each thread a strided subset in order, then a
+// tree over the threads (the same order on every call)
+__global__ __launch_bounds__(BT) void multidot_final(const double* __restrict__ partial, int nblocks,
+                                                     double* __restrict__ out) {
+  __shared__ double red[BT];
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(int64_t)b * MAXV + j];
-  out[j] = s;
+  for (int b = threadIdx.x; b < nblocks; b += BT) s += partial[(int64_t)b * MAXV + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = BT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
 }
 
 // y = alpha * y + sum_j sign * coef[j] * x_j   (coef in device memory)
@@ -85,15 +98,17 @@ size_t blas_partial_bytes() { return sizeof(double) * DOT_BLOCKS * MAXV; }
 
 hipError_t blas_multidot(int dtype, const void* X, int64_t ldx, int nv, const void* w, int64_t n, double* partial,
                          double* out, hipStream_t s) {
+  if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
   const int64_t need = (n + BT - 1) / BT;
   const int nb = (int)(need < DOT_BLOCKS ? (need < 1 ? 1 : need) : DOT_BLOCKS);
+  const dim3 grid(nb, (nv + CH - 1) / CH);
   if (dtype == SEM_F64)
-    hipLaunchKernelGGL(multidot_partial<double>, dim3(nb), dim3(BT), 0, s, static_cast<const double*>(X), ldx, nv,
+    hipLaunchKernelGGL(multidot_partial<double>, grid, dim3(BT), 0, s, static_cast<const double*>(X), ldx, nv,
                        static_cast<const double*>(w), n, partial);
   else
-    hipLaunchKernelGGL(multidot_partial<float>, dim3(nb), dim3(BT), 0, s, static_cast<const float*>(X), ldx, nv,
+    hipLaunchKernelGGL(multidot_partial<float>, grid, dim3(BT), 0, s, static_cast<const float*>(X), ldx, nv,
                        static_cast<const float*>(w), n, partial);
-  hipLaunchKernelGGL(multidot_final, dim3(1), dim3(64), 0, s, partial, nb, nv, out);
+  hipLaunchKernelGGL(multidot_final, dim3(nv), dim3(BT), 0, s, partial, nb, out);
   return hipGetLastError();
 }
 
