@@ -66,24 +66,27 @@ constexpr size_t lds_bytes(int nin, int nw) {
   return sizeof(T) * ((size_t)nw * nin * 2 * TC + (size_t)2 * nw * 2 * 8);
 }
 
+// The work of one workgroup: a row segment of one field (all values wavefront-uniform).
+struct Fast2Job {
+  int Ey, nx, ny, nw, y0, nrows;
+  int64_t nodes;  // per component
+  int64_t bo;     // values before the field (batch member or packed problem)
+  double hh[2], sc[2], nu, dt;
+};
+
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
 // 2 = o1 = a1 x1 + c1 x2 + b1 s and (when o2 is given) o2 = a2 x2 + c2 x1 + b2 s.
 template <typename T, int OP, int EP>
-__global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args g, const FastTab<T>* __restrict__ tb,
-                                                           const T* __restrict__ u, const T* __restrict__ v,
-                                                           Epi epi, Coef in_scale) {
+__device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T>* __restrict__ tb,
+                                            const T* __restrict__ u, const T* __restrict__ v, const Epi& epi,
+                                            Coef in_scale, T* __restrict__ lds) {
   constexpr bool HASV = OP != OP_RHS;
   constexpr int NIN = HASV ? 2 : 1;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* const lds = reinterpret_cast<T*>(lds_raw);
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = g.nw;
-  const int L = logical_wg(blockIdx.x, g.nwg);
-  const int bm = L / g.nseg, seg = L - bm * g.nseg;
-  const int y0 = seg * g.S;
-  const int nrows = min(g.S, g.Ey - y0);
-  const int64_t bo = (int64_t)bm * 2 * g.nodes;  // batch member offset
+  const int y0 = g.y0, nrows = g.nrows;
+  const int64_t bo = g.bo;
   const uint32_t fbytes = (uint32_t)(2 * g.nodes * sizeof(T));
   const __amdgpu_buffer_rsrc_t r_u = brsrc(u + bo, fbytes);
   const __amdgpu_buffer_rsrc_t r_v = brsrc(HASV ? v + bo : u, HASV ? fbytes : 0);
@@ -93,7 +96,7 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args g, const Fa
   const __amdgpu_buffer_rsrc_t r_x1 = brsrc(hx1 ? static_cast<const T*>(epi.x1) + bo : u, hx1 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_o2 = brsrc(ho2 ? static_cast<T*>(epi.o2) + bo : u, ho2 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_x2 = brsrc(hx2 ? static_cast<const T*>(epi.x2) + bo : u, hx2 ? fbytes : 0);
-  const double dt = g.prob->dt;
+  const double dt = g.dt;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
   const T c1 = coef<T>(epi.c1, dt), c2 = coef<T>(epi.c2, dt);
 
@@ -266,6 +269,47 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args g, const Fa
   }
 }
 
+// One field or a same-shape batch: workgroup L takes segment L % nseg of batch member L / nseg.
+template <typename T, int OP, int EP>
+__global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args a, const FastTab<T>* __restrict__ tb,
+                                                           const T* __restrict__ u, const T* __restrict__ v,
+                                                           Epi epi, Coef in_scale) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int L = logical_wg(blockIdx.x, a.nwg);
+  const int bm = L / a.nseg, seg = L - bm * a.nseg;
+  Fast2Job g;
+  g.Ey = a.Ey, g.nx = a.nx, g.ny = a.ny, g.nw = a.nw;
+  g.y0 = seg * a.S;
+  g.nrows = min(a.S, a.Ey - g.y0);
+  g.nodes = a.nodes;
+  g.bo = (int64_t)bm * 2 * a.nodes;
+  g.hh[0] = a.hh[0], g.hh[1] = a.hh[1], g.sc[0] = a.sc[0], g.sc[1] = a.sc[1], g.nu = a.nu;
+  g.dt = a.prob->dt;
+  fast2d_body<T, OP, EP>(g, tb, u, v, epi, in_scale, reinterpret_cast<T*>(lds_raw));
+}
+
+// Problems of a batched set with the same x element count: workgroup b takes work item b, a row
+// segment of one packed problem (its constants read from the problem table).
+template <typename T, int OP, int EP>
+__global__ __launch_bounds__(64 * MAXW) void fast2d_batch_kernel(const ProbDev* __restrict__ probs,
+                                                                 const Fast2Item* __restrict__ items,
+                                                                 const FastTab<T>* __restrict__ tb,
+                                                                 const T* __restrict__ u, const T* __restrict__ v,
+                                                                 Epi epi, Coef in_scale) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const Fast2Item it = items[blockIdx.x];
+  const ProbDev* __restrict__ pr = probs + it.prob;
+  Fast2Job g;
+  g.Ey = pr->E[1], g.nx = pr->n[0], g.ny = pr->n[1], g.nw = pr->E[0] / EW;
+  g.y0 = it.y0;
+  g.nrows = it.nrows;
+  g.nodes = pr->nodes;
+  g.bo = pr->off;
+  g.hh[0] = pr->hh[0], g.hh[1] = pr->hh[1], g.sc[0] = pr->sc[0], g.sc[1] = pr->sc[1], g.nu = pr->nu;
+  g.dt = pr->dt;
+  fast2d_body<T, OP, EP>(g, tb, u, v, epi, in_scale, reinterpret_cast<T*>(lds_raw));
+}
+
 // Segment length: about one workgroup per CU (256), so every workgroup starts in the first wave
 // of dispatch and the recomputed rows stay few (measured on 64 fields of 64 x 64 elements: 128,
 // 512, 1024 or 4096 workgroups are 5-50% slower for F, J v and J^T alike).  Small launches go down
@@ -336,15 +380,44 @@ template <typename T, int OP>
 hipError_t allow_lds_op() {
   constexpr int NIN = OP == OP_RHS ? 1 : 2;
   const int bytes = (int)lds_bytes<T>(NIN, MAXW);
-  hipError_t e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 0>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 1>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
-    return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 2>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fns[6] = {reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 0>),
+                        reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 1>),
+                        reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 2>),
+                        reinterpret_cast<const void*>(&fast2d_batch_kernel<T, OP, 0>),
+                        reinterpret_cast<const void*>(&fast2d_batch_kernel<T, OP, 1>),
+                        reinterpret_cast<const void*>(&fast2d_batch_kernel<T, OP, 2>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T, int OP>
+hipError_t run_batch_op(const ProbDev* probs, const Fast2Item* items, int nitems, int nw, const T* u, const T* v,
+                        const Epi& epi, Coef in_scale, const FastTab<T>* tb, hipStream_t s) {
+  constexpr int NIN = OP == OP_RHS ? 1 : 2;
+  const int ep = (epi.o2 || epi.x2) ? 2 : (epi.x1 ? 1 : 0);
+  const dim3 grid(nitems), block(64 * nw);
+  const size_t lds = lds_bytes<T>(NIN, nw);
+  if (ep == 0)
+    hipLaunchKernelGGL((fast2d_batch_kernel<T, OP, 0>), grid, block, lds, s, probs, items, tb, u, v, epi, in_scale);
+  else if (ep == 1)
+    hipLaunchKernelGGL((fast2d_batch_kernel<T, OP, 1>), grid, block, lds, s, probs, items, tb, u, v, epi, in_scale);
+  else
+    hipLaunchKernelGGL((fast2d_batch_kernel<T, OP, 2>), grid, block, lds, s, probs, items, tb, u, v, epi, in_scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_batch(const ProbDev* probs, const Fast2Item* items, int nitems, int nw, int op, const void* u,
+                     const void* v, const Epi& epi, Coef in_scale, const void* dtab, hipStream_t s) {
+  const auto* tb = static_cast<const FastTab<T>*>(dtab);
+  const T* uu = static_cast<const T*>(u);
+  const T* vv = static_cast<const T*>(v);
+  if (op == OP_RHS) return run_batch_op<T, OP_RHS>(probs, items, nitems, nw, uu, vv, epi, in_scale, tb, s);
+  if (op == OP_JAC) return run_batch_op<T, OP_JAC>(probs, items, nitems, nw, uu, vv, epi, in_scale, tb, s);
+  return run_batch_op<T, OP_JACT>(probs, items, nitems, nw, uu, vv, epi, in_scale, tb, s);
 }
 
 template <typename T>
@@ -365,6 +438,18 @@ bool fast2d_supported(const ProbDev& hp) {
 }
 
 hipError_t fast2d_prepare(int dtype) { return dtype == SEM_F64 ? allow_lds<double>() : allow_lds<float>(); }
+
+int fast2d_waves(const ProbDev& hp) { return hp.E[0] / EW; }
+
+hipError_t launch_fast2d_batch(const ProbDev* dprobs, const Fast2Item* items, int nitems, int nw, int op, const void* u,
+                               const void* v, const Epi& epi, Coef in_scale, const void* dtables, int dtype,
+                               hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  if (nw < 1 || nw > MAXW) return hipErrorInvalidValue;
+  if (dtype == SEM_F64) return run_batch<double>(dprobs, items, nitems, nw, op, u, v, epi, in_scale, dtables, s);
+  return run_batch<float>(dprobs, items, nitems, nw, op, u, v, epi, in_scale,
+                          static_cast<const char*>(dtables) + sizeof(FastTab<double>), s);
+}
 
 hipError_t launch_fast2d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, const Epi& epi,
                          Coef in_scale, const void* dtables, int dtype, hipStream_t s) {

@@ -196,12 +196,21 @@ struct OpSet {
   int pgrid = 1024;    // persistent grid size (workgroups)
   DevBuf items, ptabs64, ptabs32;
   int nitems = 0;
+  // Batched 2-D sets: the table entries [0, ngeneric) run the element + summation kernels; the
+  // rest (order 7, 8 | E_x <= 64) run the tuned 2-D kernel, one launch per x element count.
+  int ngeneric = 0;
+  struct TunedGroup {
+    int nw;  // wavefronts per workgroup (E_x / 8)
+    int nitems;
+    DevBuf items;  // Fast2Item[nitems]
+  };
+  std::vector<TunedGroup> tuned;
 
   int finalize() {
     int rc;
     if ((rc = dprob.alloc(sizeof(ProbDev) * hp.size()))) return rc;
     HIPCHK(hipMemcpy(dprob.p, hp.data(), sizeof(ProbDev) * hp.size(), hipMemcpyHostToDevice));
-    if (!fast && (rc = lvec.alloc(lvals * ts))) return rc;
+    if (!fast && lvals > 0 && (rc = lvec.alloc(lvals * ts))) return rc;
     return SEM_OK;
   }
 
@@ -211,21 +220,27 @@ struct OpSet {
                            dtype, s);
     if (fast == 2)
       return launch_fast2d(hp[0], static_cast<const ProbDev*>(dprob.p), op, u, v, epi, in_scale, fast_tab.p, dtype, s);
-    if (persistent && nitems > 0) {
-      hipError_t e = launch_persist2d(static_cast<const ProbDev*>(dprob.p), static_cast<const WorkItem*>(items.p), nitems,
-                                      pgrid, op, dtype, dtype == SEM_F64 ? ptabs64.p : ptabs32.p, u, v, lvec.p,
-                                      in_scale, s);
-      if (e != hipSuccess) return e;
-      return launch_dss(static_cast<const ProbDev*>(dprob.p), (int)hp.size(), total_nodes, dim, dtype, op != OP_JACT,
-                        lvec.p, epi, s);
+    const ProbDev* dp = static_cast<const ProbDev*>(dprob.p);
+    hipError_t e;
+    if (ngeneric > 0) {
+      if (persistent && nitems > 0) {
+        e = launch_persist2d(dp, static_cast<const WorkItem*>(items.p), nitems, pgrid, op, dtype,
+                             dtype == SEM_F64 ? ptabs64.p : ptabs32.p, u, v, lvec.p, in_scale, s);
+        if (e != hipSuccess) return e;
+      } else {
+        for (auto& c : classes) {
+          ElemLaunch el{dp + c.first, c.count, c.nitems, dim, c.P, dtype, c.epb};
+          if ((e = launch_elem(el, op, u, v, lvec.p, in_scale, c.tab.get(dtype), s)) != hipSuccess) return e;
+        }
+      }
+      if ((e = launch_dss(dp, ngeneric, total_nodes, dim, dtype, op != OP_JACT, lvec.p, epi, s)) != hipSuccess)
+        return e;
     }
-    for (auto& c : classes) {
-      ElemLaunch el{static_cast<const ProbDev*>(dprob.p) + c.first, c.count, c.nitems, dim, c.P, dtype, c.epb};
-      hipError_t e = launch_elem(el, op, u, v, lvec.p, in_scale, c.tab.get(dtype), s);
-      if (e != hipSuccess) return e;
-    }
-    return launch_dss(static_cast<const ProbDev*>(dprob.p), (int)hp.size(), total_nodes, dim, dtype, op != OP_JACT,
-                      lvec.p, epi, s);
+    for (auto& g : tuned)
+      if ((e = launch_fast2d_batch(dp, static_cast<const Fast2Item*>(g.items.p), g.nitems, g.nw, op, u, v, epi,
+                                   in_scale, fast_tab.p, dtype, s)) != hipSuccess)
+        return e;
+    return hipSuccess;
   }
 };
 
@@ -244,21 +259,28 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
   }
   os.total_vals = off[count];
   os.fast = !allow_fast || count != 1 ? 0 : fast3d_supported(tmp[0]) ? 3 : fast2d_supported(tmp[0]) ? 2 : 0;
-  // order classes
-  std::vector<int> idx(count);
-  for (int i = 0; i < count; ++i) idx[i] = i;
+  // a batched 2-D set runs its order-7 problems of 8 | E_x <= 64 on the tuned kernel: they go
+  // after every order class, so the generic launches cover a prefix of the table
+  std::vector<char> is_tuned(count, 0);
+  if (count > 1 && os.dim == 2)
+    for (int i = 0; i < count; ++i) is_tuned[i] = fast2d_supported(tmp[i]) ? 1 : 0;
+  // order classes of the generic problems
+  std::vector<int> idx;
+  for (int i = 0; i < count; ++i)
+    if (!is_tuned[i]) idx.push_back(i);
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return tmp[a].P < tmp[b].P; });
+  const int ngen = (int)idx.size();
   os.hp.clear();
   os.classes.clear();
   int64_t lv = 0, nodes0 = 0;
-  for (int k = 0; k < count;) {
+  for (int k = 0; k < ngen;) {
     int P = tmp[idx[k]].P;
     OpSet::Class c;
     c.P = P;
     c.first = (int)os.hp.size();
     c.count = 0;
     int64_t items = 0;
-    while (k < count && tmp[idx[k]].P == P) {
+    while (k < ngen && tmp[idx[k]].P == P) {
       ProbDev p = tmp[idx[k]];
       p.item0 = items;
       p.loff = lv;
@@ -277,14 +299,48 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
   }
   // item0 must be class-relative for element launches but node0 global: already so.
   os.lvals = lv;
-  if (os.dim == 2 && count > 1) {
+  os.ngeneric = ngen;
+  // tuned problems: table entries after the generic ones, grouped by x element count.  Each
+  // group's launch splits its problems into row segments of S rows, S = rows / 256 clamped to
+  // 1..4: a group's launch gets about one workgroup per CU or more, because these launches are
+  // short and latency-bound (a segment costs S + 1 row steps: the row before it is recomputed).
+  os.tuned.clear();
+  {
+    std::vector<int> tid;
+    for (int i = 0; i < count; ++i)
+      if (is_tuned[i]) tid.push_back(i);
+    std::stable_sort(tid.begin(), tid.end(), [&](int a, int b) { return tmp[a].E[0] < tmp[b].E[0]; });
+    for (size_t k = 0; k < tid.size();) {
+      const int nw = fast2d_waves(tmp[tid[k]]);
+      size_t k1 = k;
+      int64_t rows = 0;
+      for (; k1 < tid.size() && fast2d_waves(tmp[tid[k1]]) == nw; ++k1) rows += tmp[tid[k1]].E[1];
+      const int SEG = (int)std::max<int64_t>(1, std::min<int64_t>(4, rows / 256));
+      std::vector<Fast2Item> its;
+      for (; k < k1; ++k) {
+        ProbDev p = tmp[tid[k]];
+        p.item0 = p.loff = p.node0 = 0;  // unused: no element items, scratch or summation items
+        const int t = (int)os.hp.size();
+        os.hp.push_back(p);
+        for (int y0 = 0; y0 < p.E[1]; y0 += SEG) its.push_back({t, y0, std::min(SEG, p.E[1] - y0), 0});
+      }
+      OpSet::TunedGroup g;
+      g.nw = nw;
+      g.nitems = (int)its.size();
+      int rc;
+      if ((rc = g.items.alloc(sizeof(Fast2Item) * its.size()))) return rc;
+      HIPCHK(hipMemcpy(g.items.p, its.data(), sizeof(Fast2Item) * its.size(), hipMemcpyHostToDevice));
+      os.tuned.push_back(std::move(g));
+    }
+  }
+  if (os.dim == 2 && count > 1 && ngen > 0) {
     // persistent work list: chunks of whole elements per 256-thread workgroup, largest cost first
     struct It {
       WorkItem w;
       double cost;
     };
     std::vector<It> its;
-    for (size_t t = 0; t < os.hp.size(); ++t) {
+    for (size_t t = 0; t < (size_t)ngen; ++t) {
       const ProbDev& p = os.hp[t];
       const int per = persist2d_elems_per_item(p.P);
       const int64_t tot = p.nelem * p.batch;
@@ -321,6 +377,14 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     os.persistent = 1;
   }
   os.total_nodes = nodes0;
+  if (!os.tuned.empty()) {
+    int rc;
+    std::vector<char> host(fast_table_bytes());
+    fast_fill_tables(7, host.data());
+    if ((rc = os.fast_tab.alloc(host.size()))) return rc;
+    HIPCHK(hipMemcpy(os.fast_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
+    HIPCHK(fast2d_prepare(os.dtype));
+  }
   if (os.fast) {
     int rc;
     std::vector<char> host(fast_table_bytes());

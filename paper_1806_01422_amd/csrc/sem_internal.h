@@ -131,5 +131,17 @@ hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const 
                          const Epi& epi, Coef in_scale, const void* dtables, int dtype, hipStream_t s);
 hipError_t launch_fast2d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, const Epi& epi,
                          Coef in_scale, const void* dtables, int dtype, hipStream_t s);
+// Batched sets: problems that fast2d_supported accepts run the tuned 2-D kernel, one launch per
+// x element count (fast2d_waves wavefronts per workgroup) over work items = row segments.
+struct Fast2Item {
+  int32_t prob;   // index into the problem table
+  int32_t y0;     // first element row of the segment
+  int32_t nrows;  // element rows of the segment
+  int32_t pad;
+};
+int fast2d_waves(const ProbDev& hp);
+hipError_t launch_fast2d_batch(const ProbDev* dprobs, const Fast2Item* items, int nitems, int nw, int op, const void* u,
+                               const void* v, const Epi& epi, Coef in_scale, const void* dtables, int dtype,
+                               hipStream_t s);
 
 }  // namespace sem
