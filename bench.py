@@ -47,17 +47,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def event_time_ms(fn, reps):
-    """Average milliseconds per call of fn over reps calls, HIP events on the current stream."""
+def event_time_ms(fn, reps, trials=1, warmup=1):
+    """Milliseconds per call of fn: HIP events on the current stream around reps back-to-back calls,
+    after warmup calls (first-call set-up such as module load and graph capture stays out); the
+    median over trials."""
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fn()  # warm-up: first-call set-up (module load, graph capture) stays out of the timing
-    torch.cuda.synchronize()
-    s.record()
-    for _ in range(reps):
+    for _ in range(warmup):
         fn()
-    e.record()
     torch.cuda.synchronize()
-    return s.elapsed_time(e) / reps
+    per = []
+    for _ in range(trials):
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        per.append(s.elapsed_time(e) / reps)
+    return float(np.median(per))
 
 
 def c3_inputs(ctx, dtype):
@@ -117,7 +123,10 @@ def apply_2d(P):
     field and for the 64 fields of the adjoint-gradient configuration; HBM fraction from the
     algorithmic bytes (F, J v: 16 B/DOF and 24 B/DOF; J^T: 24 B/DOF)."""
     cfg = wl.C2
-    out = {"workload": "2-D 64x64 N=7 FP64, nu=1e-3: one field, and 64 fields (the gradient batch)"}
+    out = {"workload": "2-D 64x64 N=7 FP64, nu=1e-3: one field, and 64 fields (the gradient batch)",
+           "note": "one field (6.4-9.6 MB per apply) stays in the 256 MB last-level cache and is bound by launch "
+                   "and latency, so its HBM fraction is not meaningful; 64 fields (411-617 MB) are HBM-bound",
+           "timing": "HIP events, 100 applies after 10 warm-up applies, median of 5 trials"}
     for batch in (1, wl.C4.batch):
         ctx = P.Context(2, cfg.N, cfg.E, cfg.L, cfg.nu, batch=batch)
         xs = [ctx.node_coords(k) for k in range(2)]
@@ -126,10 +135,10 @@ def apply_2d(P):
         V = torch.from_numpy(wl.normal_field(ctx.shape, wl.C2_SEEDS["v"])).cuda()
         W = torch.from_numpy(wl.normal_field(ctx.shape, wl.C2_SEEDS["w"])).cuda()
         F, JV, JT = ctx.empty(), ctx.empty(), ctx.empty()
-        reps = 50
-        t_f = event_time_ms(lambda: ctx.rhs(U, F), reps)
-        t_jv = event_time_ms(lambda: ctx.jac_vec(U, V, JV), reps)
-        t_jt = event_time_ms(lambda: ctx.jact_vec(U, W, JT), reps)
+        reps = 100
+        t_f = event_time_ms(lambda: ctx.rhs(U, F), reps, trials=5, warmup=10)
+        t_jv = event_time_ms(lambda: ctx.jac_vec(U, V, JV), reps, trials=5, warmup=10)
+        t_jt = event_time_ms(lambda: ctx.jact_vec(U, W, JT), reps, trials=5, warmup=10)
         dof = ctx.ndof * batch
         out[f"fields_{batch}"] = {
             "dof": dof, "kernel_path": ctx.path, "f_us": round(t_f * 1e3, 2), "jv_us": round(t_jv * 1e3, 2),
@@ -356,14 +365,15 @@ def main():
     value = dof / (ms_step / 1e3) / 1e9  # DOF through F + J^T per second
     log(f"step (F + J^T): {ms_step:.4f} ms  ({value:.2f} GDOF/s), wall {wall:.3f} s")
 
-    reps = max(args.steps, 20)
-    t_f = event_time_ms(lambda: ctx.rhs(U, F), reps)
-    t_jt = event_time_ms(lambda: ctx.jact_vec(U, W, JT), reps)
-    t_jv = event_time_ms(lambda: ctx.jac_vec(U, V, JV), reps)
+    # single operators: 100 back-to-back applies after 10 warm-up applies, median of 5 trials
+    reps = 100
+    t_f = event_time_ms(lambda: ctx.rhs(U, F), reps, trials=5, warmup=10)
+    t_jt = event_time_ms(lambda: ctx.jact_vec(U, W, JT), reps, trials=5, warmup=10)
+    t_jv = event_time_ms(lambda: ctx.jac_vec(U, V, JV), reps, trials=5, warmup=10)
     bytes_jt = 24.0 * dof  # read u and w, write J^T w (FP64)
     achieved = bytes_jt / (t_jt / 1e3) / 1e9
     # reference: a plain elementwise streaming kernel over one field (read 8 B, write 8 B per DOF)
-    t_copy = event_time_ms(lambda: torch.neg(U, out=JV), reps)
+    t_copy = event_time_ms(lambda: torch.neg(U, out=JV), reps, trials=5, warmup=10)
     copy_gbs = 16.0 * dof / (t_copy / 1e3) / 1e9
     out = {
         "metric": "GDOF/s for F(u) and J^T w (FP64), J^T/F cost ratio, gradient/s batched vs plain",
@@ -403,8 +413,8 @@ def main():
     if want("fp32"):
         c32 = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float32)
         U32, _, W32 = c3_inputs(c32, torch.float32)
-        t_f32 = event_time_ms(lambda: c32.rhs(U32), reps)
-        t_jt32 = event_time_ms(lambda: c32.jact_vec(U32, W32), reps)
+        t_f32 = event_time_ms(lambda: c32.rhs(U32), reps, trials=5, warmup=10)
+        t_jt32 = event_time_ms(lambda: c32.jact_vec(U32, W32), reps, trials=5, warmup=10)
         c64 = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
         U64, _, W64 = c3_inputs(c64, torch.float64)
         f64, j64 = c64.rhs(U64), c64.jact_vec(U64, W64)
