@@ -64,6 +64,55 @@ __global__ __launch_bounds__(BT) void multidot_final(const double* __restrict__ 
   if (threadIdx.x == 0) out[j] = red[0];
 }
 
+// Gram-Schmidt update fused with the next reduction: y <- y + sign sum_j coef[j] x_j, then
+// partial sums of <x_j, y_new> (j < nv) or, with SELF, of <y_new, y_new> (one value); the partial
+// layout and the final reduction are those of multidot.  NV bounds nv (registers per thread).
+template <typename T, int NV, bool SELF>
+__global__ __launch_bounds__(BT) void combine_dot_partial(T* __restrict__ y, const T* __restrict__ X, int64_t ldx,
+                                                          int nv, const double* __restrict__ coef, double sign,
+                                                          int64_t n, double* __restrict__ partial) {
+  constexpr int NA = SELF ? 1 : NV;
+  __shared__ double c[MAXV];
+  __shared__ double red[BT / 64][NA];
+  if (threadIdx.x < nv) c[threadIdx.x] = sign * coef[threadIdx.x];
+  __syncthreads();
+  double acc[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (int64_t)gridDim.x * BT) {
+    double xv[NV];
+    double sum = (double)y[i];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      xv[j] = j < nv ? (double)X[j * ldx + i] : 0.0;
+      if (j < nv) sum += c[j] * xv[j];
+    }
+    const T yn = (T)sum;
+    y[i] = yn;
+    if constexpr (SELF) {
+      acc[0] += (double)yn * (double)yn;
+    } else {
+#pragma unroll
+      for (int j = 0; j < NV; ++j)
+        if (j < nv) acc[j] += xv[j] * (double)yn;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    double v = acc[j];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wave][j] = v;
+  }
+  __syncthreads();
+  const int na = SELF ? 1 : nv;
+  if ((int)threadIdx.x < na) {
+    double s = 0.0;
+    for (int k = 0; k < BT / 64; ++k) s += red[k][threadIdx.x];
+    partial[(int64_t)blockIdx.x * MAXV + threadIdx.x] = s;
+  }
+}
+
 // y = alpha * y + sum_j sign * coef[j] * x_j   (coef in device memory)
 template <typename T>
 __global__ __launch_bounds__(BT) void combine(T* __restrict__ y, double alpha, const T* __restrict__ X, int64_t ldx,
@@ -110,6 +159,42 @@ hipError_t blas_multidot(int dtype, const void* X, int64_t ldx, int nv, const vo
                        static_cast<const float*>(w), n, partial);
   hipLaunchKernelGGL(multidot_final, dim3(nv), dim3(BT), 0, s, partial, nb, out);
   return hipGetLastError();
+}
+
+template <typename T, bool SELF>
+static hipError_t run_combine_dot(T* y, const T* X, int64_t ldx, int nv, const double* coef, double sign, int64_t n,
+                                  double* partial, double* out, hipStream_t s) {
+  const int64_t need = (n + BT - 1) / BT;
+  const int nb = (int)(need < DOT_BLOCKS ? (need < 1 ? 1 : need) : DOT_BLOCKS);
+  if (nv <= 8)
+    hipLaunchKernelGGL((combine_dot_partial<T, 8, SELF>), dim3(nb), dim3(BT), 0, s, y, X, ldx, nv, coef, sign, n,
+                       partial);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((combine_dot_partial<T, 16, SELF>), dim3(nb), dim3(BT), 0, s, y, X, ldx, nv, coef, sign, n,
+                       partial);
+  else if (nv <= 32)
+    hipLaunchKernelGGL((combine_dot_partial<T, 32, SELF>), dim3(nb), dim3(BT), 0, s, y, X, ldx, nv, coef, sign, n,
+                       partial);
+  else
+    hipLaunchKernelGGL((combine_dot_partial<T, MAXV, SELF>), dim3(nb), dim3(BT), 0, s, y, X, ldx, nv, coef, sign, n,
+                       partial);
+  hipLaunchKernelGGL(multidot_final, dim3(SELF ? 1 : nv), dim3(BT), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t blas_combine_dot(int dtype, void* y, const void* X, int64_t ldx, int nv, const double* coef, double sign,
+                            int64_t n, bool self, double* partial, double* out, hipStream_t s) {
+  if (nv < 1 || nv > MAXV) return hipErrorInvalidValue;
+  if (dtype == SEM_F64) {
+    auto* yy = static_cast<double*>(y);
+    const auto* xx = static_cast<const double*>(X);
+    return self ? run_combine_dot<double, true>(yy, xx, ldx, nv, coef, sign, n, partial, out, s)
+                : run_combine_dot<double, false>(yy, xx, ldx, nv, coef, sign, n, partial, out, s);
+  }
+  auto* yy = static_cast<float*>(y);
+  const auto* xx = static_cast<const float*>(X);
+  return self ? run_combine_dot<float, true>(yy, xx, ldx, nv, coef, sign, n, partial, out, s)
+              : run_combine_dot<float, false>(yy, xx, ldx, nv, coef, sign, n, partial, out, s);
 }
 
 hipError_t blas_combine(int dtype, void* y, double alpha, const void* X, int64_t ldx, int nv, const double* coef,

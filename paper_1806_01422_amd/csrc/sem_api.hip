@@ -750,7 +750,7 @@ struct Integrator {
 struct Implicit {
   Integrator* in = nullptr;
   double* partial = nullptr;  // blas_partial_bytes()
-  double* dvec = nullptr;     // 2 * blas_max_vectors() doubles: dot results and combination weights
+  double* dvec = nullptr;     // 3 * blas_max_vectors() doubles: dot results and combination weights
   hipStream_t s = nullptr;
   double newton_rtol = 0, gmres_rtol = 0;
   int newton_maxit = 0, restart = 0, gmres_maxit = 0;
@@ -828,12 +828,20 @@ struct Implicit {
       int k = 0;
       for (; k < m && total < gmres_maxit; ++k, ++total) {
         HIPCHK(matvec(op, at, cdt, V(k), V(k + 1)));
-        if (int rc = dots(V(0), k + 1, V(k + 1), h.data())) return rc;
-        HIPCHK(blas_combine(dtype(), V(k + 1), 1.0, V(0), in->n, k + 1, dvec, -1.0, in->n, s));
-        if (int rc = dots(V(0), k + 1, V(k + 1), h2.data())) return rc;
-        HIPCHK(blas_combine(dtype(), V(k + 1), 1.0, V(0), in->n, k + 1, dvec, -1.0, in->n, s));
-        double hn = 0;
-        if (int rc = norm(V(k + 1), &hn)) return rc;
+        // w = V(k+1): h = V^T w; w -= V h fused with h2 = V^T w; w -= V h2 fused with |w|^2.
+        // Three passes over the basis, coefficients kept on the device, one host sync.
+        const int MV = blas_max_vectors();
+        HIPCHK(blas_multidot(dtype(), V(0), in->n, k + 1, V(k + 1), in->n, partial, dvec, s));
+        HIPCHK(blas_combine_dot(dtype(), V(k + 1), V(0), in->n, k + 1, dvec, -1.0, in->n, false, partial, dvec + MV,
+                                s));
+        HIPCHK(blas_combine_dot(dtype(), V(k + 1), V(0), in->n, k + 1, dvec + MV, -1.0, in->n, true, partial,
+                                dvec + 2 * MV, s));
+        double hn2 = 0;
+        HIPCHK(hipMemcpyAsync(h.data(), dvec, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h2.data(), dvec + MV, sizeof(double) * (k + 1), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hn2, dvec + 2 * MV, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double hn = std::sqrt(hn2 > 0 ? hn2 : 0.0);
         for (int i = 0; i <= k; ++i) H[i * m + k] = h[i] + h2[i];
         H[(k + 1) * m + k] = hn;
         if (hn > 0) HIPCHK(blas_axpby(dtype(), V(k + 1), 1.0 / hn, V(k + 1), 0.0, nullptr, in->n, s));
@@ -1143,7 +1151,7 @@ int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out) {
   c->integ.os = &c->os;
   c->integ.n = c->ndof * desc->batch;
   c->integ.ts = c->os.ts;
-  if ((rc = c->flag.alloc(sizeof(int))) || (rc = c->nk.alloc(blas_partial_bytes() + 2 * sizeof(double) * blas_max_vectors()))) {
+  if ((rc = c->flag.alloc(sizeof(int))) || (rc = c->nk.alloc(blas_partial_bytes() + 3 * sizeof(double) * blas_max_vectors()))) {
     delete c;
     return rc;
   }

@@ -115,6 +115,10 @@ hipError_t blas_multidot(int dtype, const void* X, int64_t ldx, int nv, const vo
 hipError_t blas_combine(int dtype, void* y, double alpha, const void* X, int64_t ldx, int nv, const double* coef,
                         double sign, int64_t n, hipStream_t s);
 hipError_t blas_axpby(int dtype, void* z, double a, const void* x, double b, const void* y, int64_t n, hipStream_t s);
+// y <- y + sign sum_j coef[j] X_j (coef in device memory), then out[j] = <X_j, y> for j < nv, or
+// with self out[0] = <y, y>: one pass over the vectors (partial as for blas_multidot)
+hipError_t blas_combine_dot(int dtype, void* y, const void* X, int64_t ldx, int nv, const double* coef, double sign,
+                            int64_t n, bool self, double* partial, double* out, hipStream_t s);
 
 // Binomial checkpointing schedule (revolve.cpp).  Actions, in order: RESTORE slot (current state
 // <- snapshot slot), ADVANCE k (k forward steps), STORE slot (snapshot slot <- current state),
