@@ -1,6 +1,7 @@
-// Building blocks shared by the tuned order-7 kernels (kern_fast2d.hip, kern_fast3d.hip): the
-// even/odd split GLL derivative table, raw buffer accesses, the 8-point line contractions and
-// the per-direction element residual contribution of the Burgers operators (Sec. 3.3).
+// Building blocks shared by the tuned kernels (kern_fast2d.hip: orders 3, 5, 7; kern_fast3d.hip:
+// order 7): the even/odd split GLL derivative table, raw buffer accesses, the line contractions
+// and the per-direction element residual contribution of the Burgers operators (Sec. 3.3).  P is
+// the number of GLL points per line (N + 1, even).
 #pragma once
 #include "sem_internal.h"
 
@@ -9,14 +10,15 @@ namespace fast {
 
 constexpr int NQ = 7;  // order
 
-// The even/odd blocks of D are A[i][m] = (D_im - D_i,7-m)/2 and B[i][m] = (D_im + D_i,7-m)/2
-// (i, m < 4).  Centro-antisymmetry makes the blocks of D^T their transposes (A' = B^T, B' = A^T),
-// so one 32-entry table serves both contractions.
-template <typename T>
+// The even/odd blocks of D are A[i][m] = (D_im - D_i,P-1-m)/2 and B[i][m] = (D_im + D_i,P-1-m)/2
+// (i, m < P/2).  Centro-antisymmetry makes the blocks of D^T their transposes (A' = B^T,
+// B' = A^T), so one table of P^2/2 entries serves both contractions.
+template <typename T, int P = 8>
 struct FastTab {
-  T A[16], B[16];
-  T w[8];            // GLL weights
-  T imq[8];          // 1 / (assembled 1-D reference mass at local index q): 1/(2 w_0) at q = 0, 7
+  static constexpr int H = P / 2;
+  T A[H * H], B[H * H];
+  T w[P];    // GLL weights
+  T imq[P];  // 1 / (assembled 1-D reference mass at local index q): 1/(2 w_0) at q = 0, P - 1
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -62,46 +64,61 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
 }
 
-// y = D x (TR = false) or y = D^T x (TR = true) on one 8-point line, even/odd split:
-//   e_m = x_m + x_{7-m}, o_m = x_m - x_{7-m};  y_i = s_i + d_i, y_{7-i} = s_i - d_i  (i < 4)
+// y = D x (TR = false) or y = D^T x (TR = true) on one P-point line, even/odd split (H = P/2):
+//   e_m = x_m + x_{P-1-m}, o_m = x_m - x_{P-1-m};  y_i = s_i + d_i, y_{P-1-i} = s_i - d_i  (i < H)
 //   D:   s_i = sum_m A[i][m] o_m,  d_i = sum_m B[i][m] e_m
 //   D^T: s_i = sum_m B[m][i] o_m,  d_i = sum_m A[m][i] e_m
-template <bool TR, typename T>
-__device__ __forceinline__ void contract(const T (&x)[8], T (&y)[8], const FastTab<T>* __restrict__ tb) {
-  const T e0 = x[0] + x[7], e1 = x[1] + x[6], e2 = x[2] + x[5], e3 = x[3] + x[4];
-  const T o0 = x[0] - x[7], o1 = x[1] - x[6], o2 = x[2] - x[5], o3 = x[3] - x[4];
+template <bool TR, typename T, int P>
+__device__ __forceinline__ void contract(const T (&x)[P], T (&y)[P], const FastTab<T, P>* __restrict__ tb) {
+  constexpr int H = P / 2;
+  T e[H], o[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    e[m] = x[m] + x[P - 1 - m];
+    o[m] = x[m] - x[P - 1 - m];
+  }
   const T* __restrict__ A = tb->A;
   const T* __restrict__ B = tb->B;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < H; ++i) {
     T s, d;
     if constexpr (!TR) {
-      s = A[4 * i] * o0 + A[4 * i + 1] * o1 + A[4 * i + 2] * o2 + A[4 * i + 3] * o3;
-      d = B[4 * i] * e0 + B[4 * i + 1] * e1 + B[4 * i + 2] * e2 + B[4 * i + 3] * e3;
+      s = A[H * i] * o[0];
+      d = B[H * i] * e[0];
+#pragma unroll
+      for (int m = 1; m < H; ++m) {
+        s += A[H * i + m] * o[m];
+        d += B[H * i + m] * e[m];
+      }
     } else {
-      s = B[i] * o0 + B[4 + i] * o1 + B[8 + i] * o2 + B[12 + i] * o3;
-      d = A[i] * e0 + A[4 + i] * e1 + A[8 + i] * e2 + A[12 + i] * e3;
+      s = B[i] * o[0];
+      d = A[i] * e[0];
+#pragma unroll
+      for (int m = 1; m < H; ++m) {
+        s += B[H * m + i] * o[m];
+        d += A[H * m + i] * e[m];
+      }
     }
     y[i] = s + d;
-    y[7 - i] = s - d;
+    y[P - 1 - i] = s - d;
   }
 }
 
 // Contribution of direction j (the lane's register direction) to the element residual of each of
-// the NC components.  ldU(i, U) / ldV(i, V) fill the 8 register values of component i of the state and of
+// the NC components.  ldU(i, U) / ldV(i, V) fill the P register values of component i of the state and of
 // the direction (J v) or scaled adjoint input Z = M^{-1} w (J^T) in the current map; emit(i, P)
 // receives the contribution to component i.  om[s] is the quadrature weight at register s (an array
 // or an indexable object),
 // K1 = nu sc_j^2, K2 = sc_j (the 2/h_j of D on the physical element folded in).
-template <typename T, int OP, int NC, typename LU, typename LV, typename OM, typename EM>
+template <typename T, int OP, int NC, int P = 8, typename LU, typename LV, typename OM, typename EM>
 __device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const OM& om, T K1, T K2,
-                                            const FastTab<T>* __restrict__ tb, EM emit) {
-  T c1[8], cu[8];
+                                            const FastTab<T, P>* __restrict__ tb, EM emit) {
+  T c1[P], cu[P];
   {
-    T Uj[8];
+    T Uj[P];
     ldU(j, Uj);
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < P; ++s) {
       c1[s] = K1 * om[s];
       cu[s] = K2 * om[s] * Uj[s];
     }
@@ -109,63 +126,63 @@ __device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const OM& om,
   if constexpr (OP == OP_RHS) {
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      T Ui[8], G[8], f[8], t[8];
+      T Ui[P], G[P], f[P], t[P];
       ldU(i, Ui);
       contract<false>(Ui, G, tb);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) f[s] = c1[s] * G[s];
+      for (int s = 0; s < P; ++s) f[s] = c1[s] * G[s];
       contract<true>(f, t, tb);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) t[s] = -(t[s] + cu[s] * G[s]);
+      for (int s = 0; s < P; ++s) t[s] = -(t[s] + cu[s] * G[s]);
       emit(i, t);
     }
   } else if constexpr (OP == OP_JAC) {
-    T cv[8];
+    T cv[P];
     {
-      T Vj[8];
+      T Vj[P];
       ldV(j, Vj);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) cv[s] = K2 * om[s] * Vj[s];
+      for (int s = 0; s < P; ++s) cv[s] = K2 * om[s] * Vj[s];
     }
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      T X[8], G[8], H[8], t[8];
+      T X[P], G[P], H[P], t[P];
       ldU(i, X);
       contract<false>(X, G, tb);
       ldV(i, X);
       contract<false>(X, H, tb);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) X[s] = c1[s] * H[s];
+      for (int s = 0; s < P; ++s) X[s] = c1[s] * H[s];
       contract<true>(X, t, tb);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) t[s] = -(t[s] + cv[s] * G[s] + cu[s] * H[s]);
+      for (int s = 0; s < P; ++s) t[s] = -(t[s] + cv[s] * G[s] + cu[s] * H[s]);
       emit(i, t);
     }
   } else {  // OP_JACT: V holds Z = M^{-1} w
-    T acc[8];
+    T acc[P];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[s] = 0;
+    for (int s = 0; s < P; ++s) acc[s] = 0;
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      T X[8], G[8];
+      T X[P], G[P];
       ldU(i, X);
       contract<false>(X, G, tb);
       ldV(i, X);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) acc[s] += X[s] * G[s];
+      for (int s = 0; s < P; ++s) acc[s] += X[s] * G[s];
     }
 #pragma unroll
-    for (int s = 0; s < 8; ++s) acc[s] *= K2 * om[s];
+    for (int s = 0; s < P; ++s) acc[s] *= K2 * om[s];
 #pragma unroll
     for (int l = 0; l < NC; ++l) {
-      T Zl[8], H[8], t[8];
+      T Zl[P], H[P], t[P];
       ldV(l, Zl);
       contract<false>(Zl, H, tb);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) H[s] = c1[s] * H[s] + cu[s] * Zl[s];
+      for (int s = 0; s < P; ++s) H[s] = c1[s] * H[s] + cu[s] * Zl[s];
       contract<true>(H, t, tb);
 #pragma unroll
-      for (int s = 0; s < 8; ++s) t[s] = (l == j) ? -(t[s] + acc[s]) : -t[s];
+      for (int s = 0; s < P; ++s) t[s] = (l == j) ? -(t[s] + acc[s]) : -t[s];
       emit(l, t);
     }
   }
@@ -183,19 +200,20 @@ __device__ __forceinline__ int logical_wg(int bid, int nwg) {
   return (nwg % 8 == 0) ? (bid % 8) * (nwg / 8) + bid / 8 : bid;
 }
 
-template <typename T>
-void fill_tab(int N, FastTab<T>* t) {
+template <typename T, int P>
+void fill_tab(FastTab<T, P>* t) {
+  constexpr int H = P / 2;
   double xi[MAXP], w[MAXP], D[MAXP * MAXP];
-  gll_tables(N, xi, w, D);
-  for (int i = 0; i < 4; ++i)
-    for (int m = 0; m < 4; ++m) {
-      const double dim = D[i * 8 + m], dimr = D[i * 8 + 7 - m];
-      t->A[4 * i + m] = (T)(0.5 * (dim - dimr));
-      t->B[4 * i + m] = (T)(0.5 * (dim + dimr));
+  gll_tables(P - 1, xi, w, D);
+  for (int i = 0; i < H; ++i)
+    for (int m = 0; m < H; ++m) {
+      const double dim = D[i * P + m], dimr = D[i * P + P - 1 - m];
+      t->A[H * i + m] = (T)(0.5 * (dim - dimr));
+      t->B[H * i + m] = (T)(0.5 * (dim + dimr));
     }
-  for (int q = 0; q < 8; ++q) {
+  for (int q = 0; q < P; ++q) {
     t->w[q] = (T)w[q];
-    t->imq[q] = (T)(1.0 / ((q == 0 || q == 7) ? 2.0 * w[0] : w[q]));
+    t->imq[q] = (T)(1.0 / ((q == 0 || q == P - 1) ? 2.0 * w[0] : w[q]));
   }
 }
 

@@ -457,12 +457,6 @@ int64_t fast3d_face_values(const ProbDev& hp) {
   return (int64_t)hp.batch * (hp.E[0] / WX) * hp.E[1] * 3 * hp.n[2] * FROWS;
 }
 
-size_t fast_table_bytes() { return sizeof(FastTab<double>) + sizeof(FastTab<float>); }
-
-void fast_fill_tables(int N, void* host) {
-  fill_tab<double>(N, static_cast<FastTab<double>*>(host));
-  fill_tab<float>(N, reinterpret_cast<FastTab<float>*>(static_cast<char*>(host) + sizeof(FastTab<double>)));
-}
 
 hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
                          const Epi& epi, Coef in_scale, const void* dtables, int dtype, hipStream_t s) {

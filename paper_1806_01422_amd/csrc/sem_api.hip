@@ -200,9 +200,11 @@ struct OpSet {
   // rest (order 7, 8 | E_x <= 64) run the tuned 2-D kernel, one launch per x element count.
   int ngeneric = 0;
   struct TunedGroup {
+    int N;   // order
     int nw;  // wavefronts per workgroup (E_x / 8)
     int nitems;
     DevBuf items;  // Fast2Item[nitems]
+    DevBuf tab;    // device tables of order N
   };
   std::vector<TunedGroup> tuned;
 
@@ -237,8 +239,8 @@ struct OpSet {
         return e;
     }
     for (auto& g : tuned)
-      if ((e = launch_fast2d_batch(dp, static_cast<const Fast2Item*>(g.items.p), g.nitems, g.nw, op, u, v, epi,
-                                   in_scale, fast_tab.p, dtype, s)) != hipSuccess)
+      if ((e = launch_fast2d_batch(dp, static_cast<const Fast2Item*>(g.items.p), g.nitems, g.nw, g.N, op, u, v, epi,
+                                   in_scale, g.tab.p, dtype, s)) != hipSuccess)
         return e;
     return hipSuccess;
   }
@@ -309,12 +311,15 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     std::vector<int> tid;
     for (int i = 0; i < count; ++i)
       if (is_tuned[i]) tid.push_back(i);
-    std::stable_sort(tid.begin(), tid.end(), [&](int a, int b) { return tmp[a].E[0] < tmp[b].E[0]; });
+    std::stable_sort(tid.begin(), tid.end(), [&](int a, int b) {
+      return tmp[a].N != tmp[b].N ? tmp[a].N < tmp[b].N : tmp[a].E[0] < tmp[b].E[0];
+    });
     for (size_t k = 0; k < tid.size();) {
-      const int nw = fast2d_waves(tmp[tid[k]]);
+      const int nw = fast2d_waves(tmp[tid[k]]), N = tmp[tid[k]].N;
       size_t k1 = k;
       int64_t rows = 0;
-      for (; k1 < tid.size() && fast2d_waves(tmp[tid[k1]]) == nw; ++k1) rows += tmp[tid[k1]].E[1];
+      for (; k1 < tid.size() && fast2d_waves(tmp[tid[k1]]) == nw && tmp[tid[k1]].N == N; ++k1)
+        rows += tmp[tid[k1]].E[1];
       const int SEG = (int)std::max<int64_t>(1, std::min<int64_t>(4, rows / 256));
       std::vector<Fast2Item> its;
       for (; k < k1; ++k) {
@@ -325,11 +330,17 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
         for (int y0 = 0; y0 < p.E[1]; y0 += SEG) its.push_back({t, y0, std::min(SEG, p.E[1] - y0), 0});
       }
       OpSet::TunedGroup g;
+      g.N = N;
       g.nw = nw;
       g.nitems = (int)its.size();
       int rc;
       if ((rc = g.items.alloc(sizeof(Fast2Item) * its.size()))) return rc;
       HIPCHK(hipMemcpy(g.items.p, its.data(), sizeof(Fast2Item) * its.size(), hipMemcpyHostToDevice));
+      std::vector<char> host(fast_table_bytes(N));
+      fast_fill_tables(N, host.data());
+      if ((rc = g.tab.alloc(host.size()))) return rc;
+      HIPCHK(hipMemcpy(g.tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
+      HIPCHK(fast2d_prepare(N, os.dtype));
       os.tuned.push_back(std::move(g));
     }
   }
@@ -377,22 +388,14 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     os.persistent = 1;
   }
   os.total_nodes = nodes0;
-  if (!os.tuned.empty()) {
-    int rc;
-    std::vector<char> host(fast_table_bytes());
-    fast_fill_tables(7, host.data());
-    if ((rc = os.fast_tab.alloc(host.size()))) return rc;
-    HIPCHK(hipMemcpy(os.fast_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
-    HIPCHK(fast2d_prepare(os.dtype));
-  }
   if (os.fast) {
     int rc;
-    std::vector<char> host(fast_table_bytes());
+    std::vector<char> host(fast_table_bytes(descs[0].order));
     fast_fill_tables(descs[0].order, host.data());
     if ((rc = os.fast_tab.alloc(host.size()))) return rc;
     HIPCHK(hipMemcpy(os.fast_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
     if (os.fast == 3 && (rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts))) return rc;
-    if (os.fast == 2) HIPCHK(fast2d_prepare(os.dtype));
+    if (os.fast == 2) HIPCHK(fast2d_prepare(descs[0].order, os.dtype));
   }
   return os.finalize();
 }

@@ -94,16 +94,17 @@ int persist2d_elems_per_item(int P);  // elements per work item for order P
 // Host GLL tables in long double (gll.cpp)
 void gll_tables(int N, double* xi, double* w, double* D);
 
-// Tuned order-7 paths (kern_fast3d.hip, kern_fast2d.hip) for one problem (any batch).  The
-// epilogue output o1 must alias neither operator input: other workgroups still read the input
-// nodes that a workgroup has finished.  Both paths take the same device table (fast_fill_tables).
+// Tuned paths (kern_fast3d.hip: 3-D order 7; kern_fast2d.hip: 2-D orders 3, 5, 7) for one
+// problem (any batch).  The epilogue output o1 must alias neither operator input: other
+// workgroups still read the input nodes that a workgroup has finished.  Both take the device
+// table of their order (fast_fill_tables).
 bool fast3d_supported(const ProbDev& hp);
 int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch
 bool fast2d_supported(const ProbDev& hp);
-// lets the 2-D kernels of dtype use their workgroup LDS (more than the default dynamic limit)
-hipError_t fast2d_prepare(int dtype);
-size_t fast_table_bytes();
-void fast_fill_tables(int N, void* host);  // fills fast_table_bytes() bytes
+// lets the 2-D kernels of order N and dtype use their workgroup LDS (more than the default limit)
+hipError_t fast2d_prepare(int N, int dtype);
+size_t fast_table_bytes(int N);            // N = 3, 5 or 7
+void fast_fill_tables(int N, void* host);  // fills fast_table_bytes(N) bytes
 
 // Vector kernels (kern_blas.hip): out[j] = <X_j, w> for nv <= blas_max_vectors() vectors X_j at
 // stride ldx (FP64 accumulation, fixed order; partial holds blas_partial_bytes()), and
@@ -136,7 +137,7 @@ hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const 
 hipError_t launch_fast2d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, const Epi& epi,
                          Coef in_scale, const void* dtables, int dtype, hipStream_t s);
 // Batched sets: problems that fast2d_supported accepts run the tuned 2-D kernel, one launch per
-// x element count (fast2d_waves wavefronts per workgroup) over work items = row segments.
+// (order, x element count) (fast2d_waves wavefronts per workgroup) over work items = row segments.
 struct Fast2Item {
   int32_t prob;   // index into the problem table
   int32_t y0;     // first element row of the segment
@@ -144,8 +145,8 @@ struct Fast2Item {
   int32_t pad;
 };
 int fast2d_waves(const ProbDev& hp);
-hipError_t launch_fast2d_batch(const ProbDev* dprobs, const Fast2Item* items, int nitems, int nw, int op, const void* u,
-                               const void* v, const Epi& epi, Coef in_scale, const void* dtables, int dtype,
-                               hipStream_t s);
+hipError_t launch_fast2d_batch(const ProbDev* dprobs, const Fast2Item* items, int nitems, int nw, int N, int op,
+                               const void* u, const void* v, const Epi& epi, Coef in_scale, const void* dtables,
+                               int dtype, hipStream_t s);
 
 }  // namespace sem

@@ -71,13 +71,15 @@ CASES = [
     # order 7 with an x element count that is a multiple of 4 runs the tuned 3-D kernel
     (3, 7, [4, 1, 1]), (3, 7, [4, 2, 3]), (3, 7, [8, 3, 2]), (3, 7, [4, 5, 1]), (3, 7, [12, 1, 2]),
     (3, 7, [8, 2, 5]), (3, 7, [4, 4, 4]),
-    # order 7 with an x element count that is a multiple of 8 (at most 64) runs the tuned 2-D
-    # kernel: one or several wavefronts per workgroup, one element row, ragged row segments
+    # orders 3, 5, 7 with an x element count that is a multiple of 8 (at most 64) run the tuned
+    # 2-D kernel: one or several wavefronts per workgroup, one element row, ragged row segments
     (2, 7, [8, 1]), (2, 7, [8, 2]), (2, 7, [8, 3]), (2, 7, [16, 5]), (2, 7, [24, 2]),
+    (2, 5, [8, 1]), (2, 5, [16, 3]), (2, 5, [40, 2]), (2, 3, [8, 2]), (2, 3, [24, 5]), (2, 3, [64, 1]),
 ]
 
 TUNED = {(2, 7, (8, 1)): 2, (2, 7, (64, 3)): 2, (3, 7, (4, 1, 1)): 3, (3, 7, (4, 4, 4)): 3, (2, 7, (5, 3)): 0,
-         (2, 7, (72, 2)): 0, (2, 9, (8, 2)): 0, (3, 7, (3, 2, 4)): 0}
+         (2, 7, (72, 2)): 0, (2, 9, (8, 2)): 0, (3, 7, (3, 2, 4)): 0, (2, 5, (8, 2)): 2, (2, 3, (16, 1)): 2,
+         (2, 4, (8, 2)): 0, (2, 6, (8, 2)): 0, (2, 1, (8, 2)): 0, (3, 5, (4, 1, 1)): 0}
 
 
 @pytest.mark.parametrize("dim,N,E", CASES)
@@ -99,7 +101,7 @@ def test_kernel_path_selection(P):
 
 
 @pytest.mark.parametrize("dim,N,E", [(1, 8, [16]), (2, 7, [5, 3]), (3, 7, [3, 2, 4]), (3, 5, [2, 2, 3]),
-                                     (3, 7, [4, 2, 3]), (2, 7, [8, 3])])
+                                     (3, 7, [4, 2, 3]), (2, 7, [8, 3]), (2, 5, [8, 3])])
 def test_operators_fp32(P, dim, N, E):
     note(f"operators fp32 dim={dim} N={N} E={E}")
     m, c = make(P, dim, N, E, nu=0.02, dtype=torch.float32)
@@ -251,7 +253,7 @@ def test_c1_trajectory_and_gradient(P):
 
 @pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1),
                                            (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2),
-                                           (2, 7, [8, 3], 2), (2, 7, [8, 1], 1)])
+                                           (2, 7, [8, 3], 2), (2, 7, [8, 1], 1), (2, 5, [8, 2], 2)])
 def test_rk4_forward_adjoint(P, dim, N, E, batch):
     note(f"RK4 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
     m, c = make(P, dim, N, E, nu=0.01, batch=batch)
@@ -344,12 +346,13 @@ def test_batch_operators_match_single(P):
 
 
 def test_batch_tuned_problems(P):
-    # a set of order-7 problems only (E_x = 8, 16, 24, 64: 1, 2, 3 and 8 wavefronts, rows split
-    # into segments of 4), plus the same set with one generic problem in front
+    # a set of tuned problems only (orders 3, 5, 7; E_x = 8, 16, 24, 64: 1, 2, 3 and 8 wavefronts),
+    # plus the same set with one generic problem in front
     note("batched set of tuned 2-D problems")
-    shapes = [(8, 3), (16, 9), (24, 2), (64, 5), (8, 8)]
+    shapes = [(7, (8, 3)), (7, (16, 9)), (5, (24, 2)), (7, (64, 5)), (3, (8, 8)), (5, (8, 1)), (3, (16, 4))]
     for extra in ([], [dict(dim=2, order=5, elems=(4, 3), length=(1.0, 1.0), nu=0.01, dt=1e-3)]):
-        specs = extra + [dict(dim=2, order=7, elems=e, length=(1.0 * e[0] / 8, 1.0), nu=0.02, dt=1e-3) for e in shapes]
+        specs = extra + [dict(dim=2, order=o, elems=e, length=(1.0 * e[0] / 8, 1.0), nu=0.02, dt=1e-3)
+                         for o, e in shapes]
         B = P.Batch(specs)
         u, v = B.empty(), B.empty()
         for i, sp in enumerate(specs):
@@ -412,7 +415,7 @@ def test_batch_trajectory_gradient(P):
 # ------------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("dim,N,E,batch", [(1, 8, [16], 1), (2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1),
                                            (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2),
-                                           (2, 7, [8, 2], 2)])
+                                           (2, 7, [8, 2], 2), (2, 3, [8, 3], 1)])
 def test_rk3_forward_adjoint(P, dim, N, E, batch):
     note(f"RK-3 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
     m, c = make(P, dim, N, E, nu=0.01, batch=batch)
