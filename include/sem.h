@@ -75,7 +75,7 @@ int sem_set_stream(sem_ctx ctx, void* stream);
 /* ndof per batch member (C * nodes) and unique nodes per component. Either pointer may be NULL. */
 int sem_query(sem_ctx ctx, int64_t* ndof, int64_t* nodes);
 /* Operator implementation the context runs (host only, no GPU work): 0 the element kernel plus
-   node summation kernel (any dimension and order), 2 the tuned 2-D order-7 kernel (x element
+   node summation kernel (any dimension and order), 2 the tuned 2-D kernel for orders 3, 5, 7 (x element
    count a multiple of 8, at most 64), 3 the tuned 3-D order-7 kernel (x element count a multiple
    of 4).  All three compute the same operators (Sec. 3.3); they differ in summation order only. */
 int sem_query_path(sem_ctx ctx, int32_t* path);

@@ -181,7 +181,7 @@ class Context:
         self.shape = (batch, dim) + tuple(reversed(self.n))
         path = _i32()
         _call(lib().sem_query_path(self._h, ctypes.byref(path)))
-        # 0: element + summation kernels, 2 / 3: tuned order-7 2-D / 3-D kernel
+        # 0: element + summation kernels, 2: tuned 2-D kernel (orders 3, 5, 7), 3: tuned 3-D kernel (order 7)
         self.path = path.value
 
     def close(self):
