@@ -197,7 +197,8 @@ struct OpSet {
   DevBuf items, ptabs64, ptabs32;
   int nitems = 0;
   // Batched 2-D sets: the table entries [0, ngeneric) run the element + summation kernels; the
-  // rest (order 7, 8 | E_x <= 64) run the tuned 2-D kernel, one launch per x element count.
+  // rest (orders 3, 5, 7 with 8 | E_x <= 64) run the tuned 2-D kernel, one launch per (order,
+  // x element count).
   int ngeneric = 0;
   struct TunedGroup {
     int N;   // order
@@ -261,8 +262,8 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
   }
   os.total_vals = off[count];
   os.fast = !allow_fast || count != 1 ? 0 : fast3d_supported(tmp[0]) ? 3 : fast2d_supported(tmp[0]) ? 2 : 0;
-  // a batched 2-D set runs its order-7 problems of 8 | E_x <= 64 on the tuned kernel: they go
-  // after every order class, so the generic launches cover a prefix of the table
+  // a batched 2-D set runs its problems of order 3, 5 or 7 with 8 | E_x <= 64 on the tuned kernel:
+  // they go after every order class, so the generic launches cover a prefix of the table
   std::vector<char> is_tuned(count, 0);
   if (count > 1 && os.dim == 2)
     for (int i = 0; i < count; ++i) is_tuned[i] = fast2d_supported(tmp[i]) ? 1 : 0;
@@ -302,7 +303,7 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
   // item0 must be class-relative for element launches but node0 global: already so.
   os.lvals = lv;
   os.ngeneric = ngen;
-  // tuned problems: table entries after the generic ones, grouped by x element count.  Each
+  // tuned problems: table entries after the generic ones, grouped by (order, x element count).  Each
   // group's launch splits its problems into row segments of S rows, S = rows / 256 clamped to
   // 1..4: a group's launch gets about one workgroup per CU or more, because these launches are
   // short and latency-bound (a segment costs S + 1 row steps: the row before it is recomputed).
