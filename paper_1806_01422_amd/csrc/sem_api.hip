@@ -1285,7 +1285,8 @@ int sem_rk4_forward(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, vo
 int sem_rk_adjoint(sem_ctx c, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam,
                    void* work) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
-  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  // with no steps there are no checkpoints to read (an empty array may come as NULL)
+  if ((!ckpt && nsteps > 0) || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
   int rc = check_scheme(scheme);
   if (rc) return rc;
   if ((rc = check_steps(dt, nsteps, K, true))) return rc;
@@ -1334,7 +1335,7 @@ int sem_cn_forward(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, voi
 int sem_cn_adjoint(sem_ctx c, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam,
                    const sem_nk_opts* opts, void* work, sem_nk_stats* stats) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
-  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  if ((!ckpt && nsteps > 0) || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
   if (lam == ckpt || lam == work || work == ckpt) return fail(SEM_ERR_ARG, "aliased buffers");
   int rc = check_steps(dt, nsteps, K, true);
   if (rc) return rc;
@@ -1595,7 +1596,7 @@ int sem_batch_rk4_forward(sem_batch b, void* u, int32_t nsteps, int32_t K, void*
 int sem_batch_rk_adjoint(sem_batch b, int32_t scheme, const void* ckpt, int32_t nsteps, int32_t K, void* lam,
                          void* work) {
   if (!b) return fail(SEM_ERR_ARG, "null batch");
-  if (!ckpt || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
+  if ((!ckpt && nsteps > 0) || !lam || !work) return fail(SEM_ERR_ARG, "null pointer");
   int rc = check_scheme(scheme);
   if (rc) return rc;
   if ((rc = check_steps(1.0, nsteps, K, true))) return rc;

@@ -620,6 +620,83 @@ def test_lmvm_other_schemes(P, scheme):
 
 
 # ------------------------------------------------------------------------------------------------
+# Degenerate inputs: empty trajectories, inviscid flow and zero fields, size limits, a batch of one
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,N,E", [(1, 8, [16]), (2, 7, [8, 2]), (2, 5, [3, 2]), (3, 7, [4, 1, 1])])
+def test_zero_steps(P, dim, N, E):
+    note(f"zero-step trajectories dim={dim} N={N} E={E}")
+    m, c = make(P, dim, N, E)
+    u, _, w = fields(m, 3)
+    U, W = gpu(u), gpu(w)
+    for scheme in ("rk4", "rk3"):
+        uT, ck = c.rk_forward(U, 1e-3, 0, 1, scheme=scheme)
+        assert torch.equal(uT, U) and ck.numel() == 0
+        assert torch.equal(c.rk_adjoint(ck, 1e-3, 0, 1, W, scheme=scheme), W)
+    uT, ck, _ = c.cn_forward(U, 1e-3, 0, 1)
+    assert torch.equal(uT, U)
+    assert torch.equal(c.cn_adjoint(ck, 1e-3, 0, 1, W)[0], W)
+    # T = 0: the gradient of 1/2 |u(T)|^2 is u_0 itself
+    u0 = U.clone().requires_grad_()
+    (0.5 * P.trajectory(u0, c, 1e-3, 0, 1).pow(2).sum()).backward()
+    assert torch.equal(u0.grad, U)
+
+
+def test_zero_steps_batch(P):
+    note("zero-step trajectories of a batched set")
+    B = P.Batch([dict(dim=2, order=5, elems=(4, 3), length=(1.0, 1.0), nu=0.01, dt=1e-3),
+                 dict(dim=2, order=7, elems=(8, 2), length=(1.0, 1.0), nu=0.02, dt=2e-3)])
+    x = gpu(wl.normal_field((B.total,), 5))
+    uT, ck = B.rk4_forward(x, 0, 1)
+    assert torch.equal(uT, x) and ck.numel() == 0
+    assert torch.equal(B.rk4_adjoint(ck, 0, 1, x), x)
+
+
+@pytest.mark.parametrize("dim,N,E", [(1, 6, [5]), (2, 5, [3, 2]), (2, 7, [8, 2]), (3, 3, [2, 2, 2]),
+                                     (3, 7, [4, 1, 2])])
+def test_inviscid_and_zero_fields(P, dim, N, E):
+    # nu = 0 (pure advection) on the generic and both tuned paths; every operator vanishes at
+    # u = 0 when nu = 0, exactly (each term carries a factor u)
+    note(f"nu = 0 and zero fields dim={dim} N={N} E={E}")
+    m, c = make(P, dim, N, E, nu=0.0)
+    u, v, w = fields(m, 11)
+    U, V, W = gpu(u), gpu(v), gpu(w)
+    assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
+    assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < TOL_APPLY
+    assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < TOL_APPLY
+    Z = torch.zeros_like(U)
+    for r in (c.rhs(Z), c.jac_vec(Z, V), c.jact_vec(Z, W)):
+        assert int(torch.count_nonzero(r)) == 0
+
+
+def test_size_limits(P):
+    note("meshes beyond the index range are rejected before any allocation")
+    with pytest.raises(P.SemError, match="too large"):
+        P.Context(3, 7, [2048, 2048, 64], [1.0, 1.0, 1.0], 0.01)  # >= 2^31 nodes per component
+    with pytest.raises(P.SemError, match="too large"):
+        P.Context(1, 8, [1 << 28], [1.0], 0.01)  # more than 2^30 grid points along a direction
+    with pytest.raises(P.SemError, match="too large"):
+        P.Context(2, 11, [4096, 4096], [1.0, 1.0], 0.01, batch=300)  # > 2^40 values in the field
+
+
+def test_batch_of_one(P):
+    # a set of one problem runs the batched machinery (no tuned single-problem kernel) and must
+    # agree with the oracle and with its own context
+    note("batched set of a single problem")
+    spec = dict(dim=2, order=5, elems=(3, 4), length=(1.0, 1.0), nu=0.02, dt=1e-3)
+    B = P.Batch([spec])
+    m = oracle.Mesh(2, 5, [3, 4], [1.0, 1.0], 0.02)
+    u, _, w = fields(m, 21)
+    U, W = gpu(u).reshape(-1), gpu(w).reshape(-1)
+    assert rel(B.rhs(U), m.rhs(u).reshape(-1)) < TOL_APPLY
+    assert rel(B.jact_vec(U, W), m.jact_vec(u, w).reshape(-1)) < TOL_APPLY
+    c = P.Context(2, 5, [3, 4], [1.0, 1.0], 0.02)
+    uT, ck = B.rk4_forward(U, 4, 2)
+    uT1, ck1 = c.rk4_forward(U.view(c.shape), 1e-3, 4, 2)
+    assert rel(uT, uT1.reshape(-1)) < TOL_TRAJ
+    assert rel(B.rk4_adjoint(ck, 4, 2, W), c.rk4_adjoint(ck1, 1e-3, 4, 2, W.view(c.shape)).reshape(-1)) < TOL_TRAJ
+
+
+# ------------------------------------------------------------------------------------------------
 # Error handling at the boundary
 # ------------------------------------------------------------------------------------------------
 def test_errors(P):
