@@ -204,7 +204,7 @@ def gradient_c5(P, nsteps=wl.C5_STEPS, K=50):
 def rk_adjoint_ratio(P, nsteps=10):
     """Forward and discrete-adjoint time per step of RK-3 and RK4 on the 3-D 32^3 N=7 FP64 field:
     checkpoints every step (the adjoint recomputes only stage states) and every 5 steps (segment
-    recompute as well)."""
+    recompute as well), and every stage stored by the forward sweep (no recompute)."""
     cfg = wl.C3
     ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
     U, _, W = c3_inputs(ctx, torch.float64)
@@ -221,6 +221,16 @@ def rk_adjoint_ratio(P, nsteps=10):
             res[f"K{K}"] = {"forward_ms_per_step": round(t_f, 4), "adjoint_ms_per_step": round(t_a, 4),
                             "adjoint_over_forward": round(t_a / t_f, 3)}
             del ck, work
+        # every stage stored by the forward sweep: the adjoint applies only the J^T products
+        uT, st = ctx.rk_forward_stored(U, dt, nsteps, scheme=scheme)
+        ctx.rk_adjoint_stored(st, dt, nsteps, W, scheme=scheme)
+        t_f = event_time_ms(lambda: ctx.rk_forward_stored(U, dt, nsteps, scheme=scheme), 3) / nsteps
+        t_a = event_time_ms(lambda: ctx.rk_adjoint_stored(st, dt, nsteps, W, scheme=scheme), 3) / nsteps
+        res["stored_stages"] = {"forward_ms_per_step": round(t_f, 4), "adjoint_ms_per_step": round(t_a, 4),
+                                "adjoint_over_forward": round(t_a / t_f, 3),
+                                "stage_states_gb": round(st.numel() * 8 / 1e9, 2)}
+        del uT, st
+        torch.cuda.empty_cache()
         out[scheme] = res
     ctx.close()
     torch.cuda.empty_cache()

@@ -125,6 +125,21 @@ int sem_rk4_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, in
 int sem_rk_forward(sem_ctx ctx, int32_t scheme, void* u, double dt, int32_t nsteps, int32_t ckpt_every, void* ckpt);
 int sem_rk_adjoint(sem_ctx ctx, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every,
                    void* lam, void* work);
+/* Every stage stored (the adjoint of Sec. 4.1 fed with the forward sweep's own stage states, as
+   an adjoint with stored stages and no checkpoint recompute does):
+   - sem_rk_stages_bytes (host only): bytes of the stage buffer for nsteps steps of the scheme:
+     nsteps * S states, S = 4 for RK4 (u_k, U2, U3, U4) and 3 for RK-3 (u_k, U2, U3).
+   - sem_rk_forward_stored: u in: u_0, out: u(T), bitwise equal to sem_rk_forward.  Writes state
+     u_k and its stage states to stages[k][s][batch][ndof] (s < S) as the stage launches form them.
+   - sem_rk_adjoint_stored: lam in: lambda_N, out: lambda_0 from those stages (read only), with the
+     same scheme, dt and nsteps: only the J^T products of each step (RK4: 4, RK-3: 3) and their
+     fused updates.  Bitwise equal to sem_rk_adjoint with the stage states stored
+     (SEM_ADJ_STORE).
+   With nsteps = 0 the stage buffer may be NULL; lam (and u) pass through unchanged.  An unknown
+   scheme, a non-positive dt or aliased buffers are SEM_ERR_ARG. */
+int sem_rk_stages_bytes(sem_ctx ctx, int32_t scheme, int32_t nsteps, int64_t* bytes);
+int sem_rk_forward_stored(sem_ctx ctx, int32_t scheme, void* u, double dt, int32_t nsteps, void* stages);
+int sem_rk_adjoint_stored(sem_ctx ctx, int32_t scheme, const void* stages, double dt, int32_t nsteps, void* lam);
 /* Binomial (revolve) checkpointing (Sec. 5.3: recompute the forward trajectory from a few stored
    states; the paper's runs use PETSc's revolve).  With `snaps` state slots the adjoint advances
    the least number of forward steps any schedule with that many slots needs.
@@ -264,6 +279,10 @@ int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t
 int sem_batch_rk_forward(sem_batch b, int32_t scheme, void* u, int32_t nsteps, int32_t ckpt_every, void* ckpt);
 int sem_batch_rk_adjoint(sem_batch b, int32_t scheme, const void* ckpt, int32_t nsteps, int32_t ckpt_every,
                          void* lam, void* work);
+/* The stored-stage pair for a batch (each problem with its own dt): stages[k][s][total]. */
+int sem_batch_rk_stages_bytes(sem_batch b, int32_t scheme, int32_t nsteps, int64_t* bytes);
+int sem_batch_rk_forward_stored(sem_batch b, int32_t scheme, void* u, int32_t nsteps, void* stages);
+int sem_batch_rk_adjoint_stored(sem_batch b, int32_t scheme, const void* stages, int32_t nsteps, void* lam);
 int sem_batch_workspace_bytes(sem_batch b, int32_t ckpt_every, int64_t* bytes);
 /* sem_set_adjoint_stages for a batch (the state is the whole packed set). */
 int sem_batch_set_adjoint_stages(sem_batch b, int32_t mode);

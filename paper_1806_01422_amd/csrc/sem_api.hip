@@ -672,6 +672,40 @@ struct Integrator {
     return SEM_OK;
   }
 
+  // Every stage stored by the forward sweep: stages[k][S][n] holds u_k and its stage states, formed
+  // by the same launches as the stage-storing segment recompute (so the same values as the
+  // captured step), and the adjoint applies only the J^T part of each step.
+  void* stage_slot(void* stages, int scheme, int k, int j) const {
+    return static_cast<char*>(stages) + ((size_t)k * stage_states(scheme) + j) * (size_t)n * ts;
+  }
+  int forward_stored(int scheme, void* u, int32_t nsteps, void* stages, hipStream_t s) {
+    if (nsteps == 0) return SEM_OK;
+    const int ns = stage_states(scheme);
+    HIPCHK(hipMemcpyAsync(stage_slot(stages, scheme, 0, 0), u, (size_t)n * ts, hipMemcpyDeviceToDevice, s));
+    for (int k = 0; k < nsteps; ++k) {
+      void* st[3] = {stage_slot(stages, scheme, k, 1), stage_slot(stages, scheme, k, 2),
+                     ns > 3 ? stage_slot(stages, scheme, k, 3) : nullptr};
+      void* unext = k + 1 < nsteps ? stage_slot(stages, scheme, k + 1, 0) : u;
+      HIPCHK(enqueue_step_stages(s, scheme, stage_slot(stages, scheme, k, 0), st, unext));
+    }
+    return SEM_OK;
+  }
+  int adjoint_stored(int scheme, const void* stages, int32_t nsteps, void* lam, hipStream_t s) {
+    if (nsteps == 0) return SEM_OK;
+    const size_t bytes = (size_t)n * ts;
+    const int ns = stage_states(scheme);
+    void* sb = const_cast<void*>(stages);  // read only
+    HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
+    for (int k = nsteps - 1; k >= 0; --k) {
+      const void* st[3] = {stage_slot(sb, scheme, k, 1), stage_slot(sb, scheme, k, 2),
+                           ns > 3 ? stage_slot(sb, scheme, k, 3) : nullptr};
+      const void* uk = stage_slot(sb, scheme, k, 0);
+      HIPCHK(scheme == SEM_RK3 ? enqueue_adjoint_jt_rk3(s, uk, st) : enqueue_adjoint_jt_rk4(s, uk, st));
+    }
+    HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
+    return SEM_OK;
+  }
+
   // Binomial checkpointing.  The forward sweep stores the schedule's first snapshots (the states
   // its actions store before the first adjoint step) into ckpt slots; the adjoint sweep copies
   // them to work and runs the rest of the schedule there.
@@ -1235,6 +1269,25 @@ int sem_set_check_finite(sem_ctx c, int32_t on) {
   return SEM_OK;
 }
 
+// With sem_set_check_finite on: SEM_ERR_NONFINITE if the final state holds a non-finite value.
+static int check_final_state(sem_ctx c, const void* u, double dt) {
+  if (!c->check_finite) return SEM_OK;
+  HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
+  const int64_t n = c->integ.n;
+  if (c->d.dtype == SEM_F64)
+    hipLaunchKernelGGL(finite_kernel<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double*>(u), n,
+                       static_cast<int*>(c->flag.p));
+  else
+    hipLaunchKernelGGL(finite_kernel<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float*>(u), n,
+                       static_cast<int*>(c->flag.p));
+  HIPCHK(hipGetLastError());
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (h) return fail(SEM_ERR_NONFINITE, "trajectory produced a non-finite value (dt = %g too large?)", dt);
+  return SEM_OK;
+}
+
 int sem_rk_forward(sem_ctx c, int32_t scheme, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
   if (!u) return fail(SEM_ERR_ARG, "null u");
@@ -1245,22 +1298,41 @@ int sem_rk_forward(sem_ctx c, int32_t scheme, void* u, double dt, int32_t nsteps
   if ((rc = c->integ.prepare(scheme))) return rc;
   if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
   if ((rc = c->integ.forward(scheme, u, nsteps, K, ckpt, c->stream))) return rc;
-  if (c->check_finite) {
-    HIPCHK(hipMemsetAsync(c->flag.p, 0, sizeof(int), c->stream));
-    const int64_t n = c->integ.n;
-    if (c->d.dtype == SEM_F64)
-      hipLaunchKernelGGL(finite_kernel<double>, dim3(1024), dim3(256), 0, c->stream, static_cast<const double*>(u), n,
-                         static_cast<int*>(c->flag.p));
-    else
-      hipLaunchKernelGGL(finite_kernel<float>, dim3(1024), dim3(256), 0, c->stream, static_cast<const float*>(u), n,
-                         static_cast<int*>(c->flag.p));
-    HIPCHK(hipGetLastError());
-    int h = 0;
-    HIPCHK(hipMemcpyAsync(&h, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (h) return fail(SEM_ERR_NONFINITE, "trajectory produced a non-finite value (dt = %g too large?)", dt);
-  }
+  return check_final_state(c, u, dt);
+}
+
+int sem_rk_stages_bytes(sem_ctx c, int32_t scheme, int32_t nsteps, int64_t* bytes) {
+  if (!c || !bytes) return fail(SEM_ERR_ARG, "null argument");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(SEM_ERR_ARG, "nsteps %d < 0", nsteps);
+  *bytes = (int64_t)nsteps * Integrator::stage_states(scheme) * c->integ.n * (int64_t)c->os.ts;
   return SEM_OK;
+}
+
+int sem_rk_forward_stored(sem_ctx c, int32_t scheme, void* u, double dt, int32_t nsteps, void* stages) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!u || (!stages && nsteps > 0)) return fail(SEM_ERR_ARG, "null pointer");
+  if (stages == u) return fail(SEM_ERR_ARG, "stages alias u");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if ((rc = check_steps(dt, nsteps, 1, false))) return rc;
+  if ((rc = c->integ.alloc_buffers())) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  if ((rc = c->integ.forward_stored(scheme, u, nsteps, stages, c->stream))) return rc;
+  return check_final_state(c, u, dt);
+}
+
+int sem_rk_adjoint_stored(sem_ctx c, int32_t scheme, const void* stages, double dt, int32_t nsteps, void* lam) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!lam || (!stages && nsteps > 0)) return fail(SEM_ERR_ARG, "null pointer");
+  if (stages == lam) return fail(SEM_ERR_ARG, "stages alias lam");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if ((rc = check_steps(dt, nsteps, 1, false))) return rc;
+  if ((rc = c->integ.alloc_buffers())) return rc;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  return c->integ.adjoint_stored(scheme, stages, nsteps, lam, c->stream);
 }
 
 int sem_workspace_bytes(sem_ctx c, int32_t K, int64_t* bytes) {
@@ -1607,6 +1679,37 @@ int sem_batch_rk_adjoint(sem_batch b, int32_t scheme, const void* ckpt, int32_t 
 
 int sem_batch_rk4_adjoint(sem_batch b, const void* ckpt, int32_t nsteps, int32_t K, void* lam, void* work) {
   return sem_batch_rk_adjoint(b, SEM_RK4, ckpt, nsteps, K, lam, work);
+}
+
+int sem_batch_rk_stages_bytes(sem_batch b, int32_t scheme, int32_t nsteps, int64_t* bytes) {
+  if (!b || !bytes) return fail(SEM_ERR_ARG, "null argument");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(SEM_ERR_ARG, "nsteps %d < 0", nsteps);
+  *bytes = (int64_t)nsteps * Integrator::stage_states(scheme) * b->integ.n * (int64_t)b->os.ts;
+  return SEM_OK;
+}
+
+int sem_batch_rk_forward_stored(sem_batch b, int32_t scheme, void* u, int32_t nsteps, void* stages) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (!u || (!stages && nsteps > 0)) return fail(SEM_ERR_ARG, "null pointer");
+  if (stages == u) return fail(SEM_ERR_ARG, "stages alias u");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if ((rc = check_steps(1.0, nsteps, 1, false))) return rc;
+  if ((rc = b->integ.alloc_buffers())) return rc;
+  return b->integ.forward_stored(scheme, u, nsteps, stages, b->stream);
+}
+
+int sem_batch_rk_adjoint_stored(sem_batch b, int32_t scheme, const void* stages, int32_t nsteps, void* lam) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  if (!lam || (!stages && nsteps > 0)) return fail(SEM_ERR_ARG, "null pointer");
+  if (stages == lam) return fail(SEM_ERR_ARG, "stages alias lam");
+  int rc = check_scheme(scheme);
+  if (rc) return rc;
+  if ((rc = check_steps(1.0, nsteps, 1, false))) return rc;
+  if ((rc = b->integ.alloc_buffers())) return rc;
+  return b->integ.adjoint_stored(scheme, stages, nsteps, lam, b->stream);
 }
 
 int sem_batch_configure(sem_batch b, int32_t persistent, int32_t param) {

@@ -109,6 +109,12 @@ _SIGS = {
     "sem_rk_adjoint": [_vp, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
     "sem_batch_rk_forward": [_vp, _i32, _vp, _i32, _i32, _vp],
     "sem_batch_rk_adjoint": [_vp, _i32, _vp, _i32, _i32, _vp, _vp],
+    "sem_rk_stages_bytes": [_vp, _i32, _i32, ctypes.POINTER(_i64)],
+    "sem_rk_forward_stored": [_vp, _i32, _vp, _f64, _i32, _vp],
+    "sem_rk_adjoint_stored": [_vp, _i32, _vp, _f64, _i32, _vp],
+    "sem_batch_rk_stages_bytes": [_vp, _i32, _i32, ctypes.POINTER(_i64)],
+    "sem_batch_rk_forward_stored": [_vp, _i32, _vp, _i32, _vp],
+    "sem_batch_rk_adjoint_stored": [_vp, _i32, _vp, _i32, _vp],
     "sem_batch_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
     "sem_batch_set_adjoint_stages": [_vp, _i32],
     "sem_batch_configure": [_vp, _i32, _i32],
@@ -303,6 +309,31 @@ class Context:
                                    _ptr(work)))
         return lam
 
+    def stage_states(self, scheme="rk4"):
+        """States stored per step by rk_forward_stored: u_k and the stage states."""
+        return 4 if _scheme(scheme) == _scheme("rk4") else 3
+
+    def rk_forward_stored(self, u0, dt, nsteps, scheme="rk4"):
+        """(u(T), stages [nsteps][S][batch][C][...]): every step's state and stage states."""
+        self._chk(u0, "u0")
+        code = _scheme(scheme)
+        u = u0.clone()
+        st = torch.empty((nsteps, self.stage_states(scheme)) + self.shape, dtype=self.dtype, device="cuda")
+        self._bind()
+        _call(lib().sem_rk_forward_stored(self._h, code, _ptr(u), float(dt), int(nsteps), _ptr(st)))
+        return u, st
+
+    def rk_adjoint_stored(self, stages, dt, nsteps, lamT, scheme="rk4"):
+        """lambda_0 from lambda_N with the stage states stored by rk_forward_stored (J^T only)."""
+        self._chk(lamT, "lamT")
+        if not stages.is_contiguous() or stages.dtype != self.dtype or \
+                stages.numel() != nsteps * self.stage_states(scheme) * self.batch * self.ndof:
+            raise SemError("stages must be the contiguous array rk_forward_stored returned")
+        lam = lamT.clone()
+        self._bind()
+        _call(lib().sem_rk_adjoint_stored(self._h, _scheme(scheme), _ptr(stages), float(dt), int(nsteps), _ptr(lam)))
+        return lam
+
 
     def _nk(self, opts):
         o = NkOpts()
@@ -471,6 +502,28 @@ def trajectory_revolve(u0, sem, dt, nsteps, snaps, scheme="rk4"):
     return SEMTrajectoryRevolve.apply(u0, sem, dt, nsteps, snaps, scheme)
 
 
+class SEMTrajectoryStored(torch.autograd.Function):
+    """SEMTrajectory with every stage state stored by the forward sweep: the backward applies only
+    the J^T products (no recompute), at nsteps * S states of memory."""
+
+    @staticmethod
+    def forward(ctx, u0, sem, dt, nsteps, scheme="rk4"):
+        uT, st = sem.rk_forward_stored(u0.contiguous(), dt, nsteps, scheme=scheme)
+        ctx.sem, ctx.dt, ctx.nsteps, ctx.scheme = sem, dt, nsteps, scheme
+        ctx.save_for_backward(st)
+        return uT
+
+    @staticmethod
+    def backward(ctx, g):
+        (st,) = ctx.saved_tensors
+        lam0 = ctx.sem.rk_adjoint_stored(st, ctx.dt, ctx.nsteps, g.contiguous(), scheme=ctx.scheme)
+        return lam0, None, None, None, None
+
+
+def trajectory_stored(u0, sem, dt, nsteps, scheme="rk4"):
+    return SEMTrajectoryStored.apply(u0, sem, dt, nsteps, scheme)
+
+
 class Batch:
     """Independent 2-D (or 1-D/3-D, shared dim) problems of uneven size/order packed back to back."""
 
@@ -576,6 +629,26 @@ class Batch:
         work = self._work(ckpt_every, work)
         _call(lib().sem_batch_rk_adjoint(self._h, code, _ptr(ckpt), int(nsteps), int(ckpt_every), _ptr(lam),
                                          _ptr(work)))
+        return lam
+
+    def rk_forward_stored(self, u0, nsteps, scheme="rk4"):
+        """(u(T), stages [nsteps][S][total]) as Context.rk_forward_stored, each problem with its dt."""
+        self._chk(u0, "u0")
+        code = _scheme(scheme)
+        u = u0.clone()
+        S = 4 if code == _scheme("rk4") else 3
+        st = torch.empty((nsteps, S, self.total), dtype=self.dtype, device="cuda")
+        _call(lib().sem_batch_rk_forward_stored(self._h, code, _ptr(u), int(nsteps), _ptr(st)))
+        return u, st
+
+    def rk_adjoint_stored(self, stages, nsteps, lamT, scheme="rk4"):
+        self._chk(lamT, "lamT")
+        code = _scheme(scheme)
+        S = 4 if code == _scheme("rk4") else 3
+        if not stages.is_contiguous() or stages.dtype != self.dtype or stages.numel() != nsteps * S * self.total:
+            raise SemError("stages must be the contiguous array rk_forward_stored returned")
+        lam = lamT.clone()
+        _call(lib().sem_batch_rk_adjoint_stored(self._h, code, _ptr(stages), int(nsteps), _ptr(lam)))
         return lam
 
     def configure(self, persistent, param=0):

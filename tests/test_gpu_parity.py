@@ -292,6 +292,66 @@ def test_adjoint_stage_modes(P, scheme, dim, N, E, batch):
     assert c.workspace_bytes(K) == wr  # these states are small: recompute by default
 
 
+@pytest.mark.parametrize("scheme", ["rk4", "rk3"])
+@pytest.mark.parametrize("dim,N,E,batch", [(1, 8, [16], 1), (2, 7, [8, 3], 2), (2, 5, [4, 3], 1), (3, 7, [4, 1, 2], 1),
+                                           (3, 5, [2, 2, 2], 1)])
+def test_stored_stages(P, scheme, dim, N, E, batch):
+    # every stage stored by the forward sweep: the same states as the checkpointed forward (bitwise),
+    # and the J^T-only adjoint equals the adjoint with stage states stored per segment (bitwise)
+    note(f"stored stages {scheme} dim={dim} N={N} E={E} batch={batch}")
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    u, _, w = fields(m, 41)
+    dt, n, K = (2e-3 if dim > 1 else 2e-4), 8, 2
+    U, W = gpu(u), gpu(w)
+    uT, st = c.rk_forward_stored(U, dt, n, scheme=scheme)
+    uT1, ck = c.rk_forward(U, dt, n, K, scheme=scheme)
+    assert st.shape == (n, c.stage_states(scheme)) + c.shape
+    assert torch.equal(uT, uT1)
+    for j in range(n // K):
+        assert torch.equal(st[j * K, 0], ck[j])
+    lam = c.rk_adjoint_stored(st, dt, n, W, scheme=scheme)
+    c.set_adjoint_stages("store")
+    lam1 = c.rk_adjoint(ck, dt, n, K, W, scheme=scheme)
+    c.set_adjoint_stages("auto")
+    assert torch.equal(lam, lam1)
+    uT_ref, ck_ref = m.erk_forward(scheme, u, dt, n, K)
+    assert rel(uT, uT_ref) < TOL_TRAJ
+    assert rel(lam, m.erk_adjoint(scheme, ck_ref, dt, n, K, w)) < TOL_TRAJ
+    # through autograd
+    u0 = U.clone().requires_grad_()
+    (0.5 * P.trajectory_stored(u0, c, dt, n, scheme).pow(2).sum()).backward()
+    assert rel(u0.grad, m.erk_adjoint(scheme, ck_ref, dt, n, K, uT_ref)) < TOL_TRAJ
+
+
+def test_stored_stages_batch_and_errors(P):
+    note("stored stages: batched set, zero steps, argument errors")
+    specs, probs = batch_problems(12)
+    B = P.Batch(specs)
+    x = gpu(wl.normal_field((B.total,), 3)) * 0.01
+    lamT = gpu(wl.normal_field((B.total,), 4))
+    for scheme in ("rk4", "rk3"):
+        uT, st = B.rk_forward_stored(x, 6, scheme=scheme)
+        uT1, ck = B.rk_forward(x, 6, 3, scheme=scheme)
+        assert torch.equal(uT, uT1)
+        B.set_adjoint_stages("store")
+        assert torch.equal(B.rk_adjoint_stored(st, 6, lamT, scheme=scheme), B.rk_adjoint(ck, 6, 3, lamT, scheme=scheme))
+        B.set_adjoint_stages("auto")
+        uT0, st0 = B.rk_forward_stored(x, 0, scheme=scheme)
+        assert torch.equal(uT0, x) and st0.numel() == 0
+        assert torch.equal(B.rk_adjoint_stored(st0, 0, lamT, scheme=scheme), lamT)
+    m, c = make(P, 2, 3, [2, 2])
+    u = torch.zeros(c.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.SemError):
+        c.rk_forward_stored(u, -1.0, 2)
+    with pytest.raises(P.SemError):
+        c.rk_forward_stored(u, 1e-3, 2, scheme="cn")  # implicit scheme: no stage states
+    _, st = c.rk_forward_stored(u, 1e-3, 2)
+    with pytest.raises(P.SemError):
+        c.rk_adjoint_stored(st, 1e-3, 3, u)  # stage array of another length
+    with pytest.raises(P.SemError):
+        P.sem._call(P.lib().sem_rk_adjoint_stored(c._h, 0, P.sem._ptr(st), 1e-3, 2, P.sem._ptr(st)))  # aliasing
+
+
 def test_c4_shape_batch_gradient(P):
     # the 64-IC 2-D configuration at full mesh size; a 50-step horizon keeps the oracle side short.
     cfg = wl.C4
