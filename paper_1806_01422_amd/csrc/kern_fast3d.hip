@@ -51,7 +51,8 @@ constexpr int FSEC = 13;   // 32-byte sectors the fixup completes per (workgroup
 
 struct FastArgs {
   int Ex, Ey, Ez, nx, ny, nz;
-  int NX, NWG;  // workgroups along x (Ex / 4) and per field (NX * Ey)
+  int NX, NWG;  // workgroups along x (Ex / 4) and per field and z-segment (NX * Ey)
+  int nseg, S;  // z-segments per column and element layers per segment
   double hh[3], sc[3], nu;
   double ihhh;    // 1 / (h_x h_y h_z)
   int64_t nodes;  // per component
@@ -66,7 +67,8 @@ __device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b 
 
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
 // 2 = o1 = a1 x1 + c1 x2 + b1 s and (when o2 is given) o2 = a2 x2 + c2 x1 + b2 s.
-template <typename T, int OP, int EP>
+// SEG: the z-sweep split into g.nseg segments (else one sweep closed by the periodic wrap).
+template <typename T, int OP, int EP, bool SEG>
 __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                      const T* __restrict__ u, const T* __restrict__ v,
                                                      T* __restrict__ face, Epi epi, Coef in_scale) {
@@ -77,7 +79,8 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   __shared__ T sEx[2][3][3][64];  // [step parity][sending wavefront][component][x-map lane]
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int L = logical_wg(blockIdx.x, g.NWG);
+  const int LS = logical_wg(blockIdx.x, g.NWG * (SEG ? g.nseg : 1));
+  const int seg = SEG ? LS / g.NWG : 0, L = LS - seg * g.NWG;
   const int X = L % g.NX, ey = L / g.NX;
   const int ex = WX * X + wave;
   const int64_t bo = (int64_t)blockIdx.y * 3 * g.nodes;  // batch member offset
@@ -189,11 +192,21 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
   T* __restrict__ tU = sU[wave][0];
   T* __restrict__ tQ = sQ[wave][0];
   T* __restrict__ tV = HASV ? sV[wave][0] : sU[wave][0];
+  // The sweep.  One segment (wrap): layers 0 .. Ez - 1, plane c = 0 of layer 0 completed by the
+  // periodic wrap after the sweep.  Several: layers z0 .. z0 + nl - 1 after a first step that
+  // recomputes layer z0 - 1 (periodically) without storing, so that the carry into plane 0 of
+  // layer z0 is complete and every plane is stored by the segment that owns it.
+  constexpr bool wrap = !SEG;
+  const int z0 = seg * g.S, nl = min(g.S, g.Ez - z0);
+  const int nstep = wrap ? g.Ez : nl + 1;
+  const int zfirst = wrap ? 0 : (z0 == 0 ? g.Ez - 1 : z0 - 1);
   T cu[3][8], cv[3][8];
-  load_z(0, 0, cu, cv);
+  load_z(zfirst, 0, cu, cv);
   T carry[3] = {0, 0, 0}, first0[3] = {0, 0, 0};
 
-  for (int ez = 0; ez < g.Ez; ++ez) {
+  for (int k = 0; k < nstep; ++k) {
+    const int ez = wrap ? k : (k == 0 ? zfirst : z0 + k - 1);
+    const int c_lo = (wrap && k == 0) ? 1 : 0, c_hi = (wrap || k > 0) ? 7 : 0;  // planes stored
     // ---- z-map (lane (a=l0, b=l1), register c): stage the element tile, z-direction part
     T wlast[3];  // unscaled input plane c = 7, the next layer's plane c = 0
 #pragma unroll
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
       cu[i][0] = cu[i][7];
       if constexpr (HASV) cv[i][0] = wlast[i];
     }
-    load_z(ez + 1 < g.Ez ? ez + 1 : 0, 1, cu, cv);
+    load_z(ez + 1 < g.Ez ? ez + 1 : 0, 1, cu, cv);  // the last step loads one layer more
     wave_sync();
     // ---- y-map (lane (a=l0, c=l1), register b)
     map_contrib<T, OP, 3>(
@@ -281,10 +294,10 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
         });
     // epilogue operands of this layer: issued before the barrier so that their latency overlaps it
     T E1[3][7], E2[3][7];
-    load_epi(ez, E1, E2, ez == 0 ? 1 : 0, 7);
+    load_epi(ez, E1, E2, c_lo, c_hi);
     // ---- x-direction summation inside the workgroup: wavefront w's face a = 7 is wavefront
     // w + 1's face a = 0 (double-buffered by step parity: one barrier per step)
-    const int par = ez & 1;
+    const int par = k & 1;
     if (wave < WX - 1) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) sEx[par][wave][i][lane] = R7[i];
@@ -306,15 +319,15 @@ __global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T
       Zv[i][0] += carry[i];
       carry[i] = Zv[i][7];
     }
-    if (ez == 0) {
+    if (wrap && k == 0) {
 #pragma unroll
       for (int i = 0; i < 3; ++i) first0[i] = Zv[i][0];
     }
-    // ---- outputs (plane c = 0 of layer 0 waits for the periodic wrap)
-    emit(ez, Zv, ez == 0 ? 1 : 0, 7, E1, E2);
+    // ---- outputs (with one segment, plane c = 0 of layer 0 waits for the periodic wrap)
+    emit(ez, Zv, c_lo, c_hi, E1, E2);
   }
   // periodic wrap along z: the carried plane of the last layer is plane c = 0 of layer 0
-  {
+  if (wrap) {
     T Zv[3][8], E1[3][7], E2[3][7];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -389,7 +402,12 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   }
 }
 
-FastArgs make_args(const ProbDev& hp, const ProbDev* dprob) {
+// z-segments per column: the FP32 F kernel (54 KB of LDS, at most 256 registers) fits two
+// workgroups per CU, which needs twice as many workgroups as CUs; every other variant holds one
+// workgroup per CU, where a segment would only add its recomputed layer.
+int z_segments(const ProbDev& hp, int op, bool f32) { return (f32 && op == OP_RHS && hp.E[2] >= 4) ? 2 : 1; }
+
+FastArgs make_args(const ProbDev& hp, const ProbDev* dprob, int nseg) {
   FastArgs g;
   g.Ex = hp.E[0];
   g.Ey = hp.E[1];
@@ -399,6 +417,8 @@ FastArgs make_args(const ProbDev& hp, const ProbDev* dprob) {
   g.nz = hp.n[2];
   g.NX = hp.E[0] / WX;
   g.NWG = g.NX * hp.E[1];
+  g.nseg = nseg;
+  g.S = (hp.E[2] + nseg - 1) / nseg;
   for (int k = 0; k < 3; ++k) {
     g.hh[k] = hp.hh[k];
     g.sc[k] = hp.sc[k];
@@ -413,20 +433,29 @@ FastArgs make_args(const ProbDev& hp, const ProbDev* dprob) {
 template <typename T>
 hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
                     const Epi& epi, Coef in_scale, const void* dtab, hipStream_t s) {
-  const FastArgs g = make_args(hp, dprob);
+  const FastArgs g = make_args(hp, dprob, z_segments(hp, op, sizeof(T) == 4));
   const auto* tb = static_cast<const FastTab<T>*>(dtab);
-  const dim3 grid(g.NWG, hp.batch);
+  const dim3 grid(g.NWG * g.nseg, hp.batch);
   T* fc = static_cast<T*>(face);
   const T* uu = static_cast<const T*>(u);
   const T* vv = static_cast<const T*>(v);
   const int ep = (epi.o2 || epi.x2) ? 2 : (epi.x1 ? 1 : 0);
 #define SEM_FAST_LAUNCH(OPV, EPV)                                                                           \
-  hipLaunchKernelGGL((fast3d_kernel<T, OPV, EPV>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale)
+  hipLaunchKernelGGL((fast3d_kernel<T, OPV, EPV, false>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale)
 #define SEM_FAST_EP(OPV)          \
   if (ep == 0) SEM_FAST_LAUNCH(OPV, 0); \
   else if (ep == 1) SEM_FAST_LAUNCH(OPV, 1); \
   else SEM_FAST_LAUNCH(OPV, 2);
-  if (op == OP_RHS) {
+  if (op == OP_RHS && g.nseg > 1) {
+    if constexpr (sizeof(T) == 4) {  // the only segmented variant (z_segments)
+      if (ep == 0)
+        hipLaunchKernelGGL((fast3d_kernel<T, OP_RHS, 0, true>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale);
+      else if (ep == 1)
+        hipLaunchKernelGGL((fast3d_kernel<T, OP_RHS, 1, true>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale);
+      else
+        hipLaunchKernelGGL((fast3d_kernel<T, OP_RHS, 2, true>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale);
+    }
+  } else if (op == OP_RHS) {
     SEM_FAST_EP(OP_RHS)
   } else if (op == OP_JAC) {
     SEM_FAST_EP(OP_JAC)

@@ -100,8 +100,11 @@ def test_kernel_path_selection(P):
         assert c.path == path, (dim, N, E, c.path)
 
 
+# 3-D order 7 with E_x % 4 = 0 and at least 4 element layers: the FP32 F kernel sweeps z in two
+# segments (the second one ragged for odd E_z), each recomputing the layer before it
 @pytest.mark.parametrize("dim,N,E", [(1, 8, [16]), (2, 7, [5, 3]), (3, 7, [3, 2, 4]), (3, 5, [2, 2, 3]),
-                                     (3, 7, [4, 2, 3]), (2, 7, [8, 3]), (2, 5, [8, 3])])
+                                     (3, 7, [4, 2, 3]), (2, 7, [8, 3]), (2, 5, [8, 3]), (3, 7, [4, 1, 4]),
+                                     (3, 7, [4, 2, 5]), (3, 7, [8, 1, 7])])
 def test_operators_fp32(P, dim, N, E):
     note(f"operators fp32 dim={dim} N={N} E={E}")
     m, c = make(P, dim, N, E, nu=0.02, dtype=torch.float32)
@@ -110,6 +113,20 @@ def test_operators_fp32(P, dim, N, E):
     assert rel(c.rhs(U), m.rhs(u)) < 1e-4
     assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < 1e-4
     assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < 1e-4
+
+
+@pytest.mark.parametrize("E", [[4, 1, 4], [4, 2, 5]])
+def test_rk4_fp32_3d(P, E):
+    # FP32 trajectories on the tuned 3-D kernels (z-segmented F with its epilogue variants, J^T)
+    note(f"RK4 fp32 3-D E={E}")
+    m, c = make(P, 3, 7, E, nu=0.01, dtype=torch.float32)
+    u, _, w = fields(m, 23)
+    dt, n, K = 2e-3, 6, 3
+    uT_ref, ck_ref = m.rk4_forward(u, dt, n, K)
+    uT, ck = c.rk4_forward(gpu(u, torch.float32), dt, n, K)
+    assert rel(uT, uT_ref) < 1e-4
+    lam = c.rk4_adjoint(ck, dt, n, K, gpu(w, torch.float32))
+    assert rel(lam, m.rk4_adjoint(ck_ref, dt, n, K, w)) < 1e-4
 
 
 @pytest.mark.parametrize("dim,N", [(1, 4), (2, 4), (3, 4), (3, 7)])
