@@ -67,9 +67,10 @@ __device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b 
 
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
 // 2 = o1 = a1 x1 + c1 x2 + b1 s and (when o2 is given) o2 = a2 x2 + c2 x1 + b2 s.
-// SEG: the z-sweep split into g.nseg segments (else one sweep closed by the periodic wrap).
+// SEG: the z-sweep split into g.nseg segments (else one sweep closed by the periodic wrap), for
+// two workgroups per CU: the register budget is then that of two wavefronts per SIMD.
 template <typename T, int OP, int EP, bool SEG>
-__global__ __launch_bounds__(256) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
+__global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                      const T* __restrict__ u, const T* __restrict__ v,
                                                      T* __restrict__ face, Epi epi, Coef in_scale) {
   constexpr bool HASV = OP != OP_RHS;
@@ -405,7 +406,9 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
 // z-segments per column: the FP32 F kernel (54 KB of LDS, at most 256 registers) fits two
 // workgroups per CU, which needs twice as many workgroups as CUs; every other variant holds one
 // workgroup per CU, where a segment would only add its recomputed layer.
-int z_segments(const ProbDev& hp, int op, bool f32) { return (f32 && op == OP_RHS && hp.E[2] >= 4) ? 2 : 1; }
+int z_segments(const ProbDev& hp, int op, bool f32) {
+  return (f32 && (op == OP_RHS || op == OP_JACT) && hp.E[2] >= 4) ? 2 : 1;
+}
 
 FastArgs make_args(const ProbDev& hp, const ProbDev* dprob, int nseg) {
   FastArgs g;
@@ -446,14 +449,19 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
   if (ep == 0) SEM_FAST_LAUNCH(OPV, 0); \
   else if (ep == 1) SEM_FAST_LAUNCH(OPV, 1); \
   else SEM_FAST_LAUNCH(OPV, 2);
-  if (op == OP_RHS && g.nseg > 1) {
-    if constexpr (sizeof(T) == 4) {  // the only segmented variant (z_segments)
-      if (ep == 0)
-        hipLaunchKernelGGL((fast3d_kernel<T, OP_RHS, 0, true>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale);
-      else if (ep == 1)
-        hipLaunchKernelGGL((fast3d_kernel<T, OP_RHS, 1, true>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale);
-      else
-        hipLaunchKernelGGL((fast3d_kernel<T, OP_RHS, 2, true>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale);
+#define SEM_FAST_LAUNCH_SEG(OPV, EPV)                                                                       \
+  hipLaunchKernelGGL((fast3d_kernel<T, OPV, EPV, true>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale)
+#define SEM_FAST_EP_SEG(OPV)                \
+  if (ep == 0) SEM_FAST_LAUNCH_SEG(OPV, 0); \
+  else if (ep == 1) SEM_FAST_LAUNCH_SEG(OPV, 1); \
+  else SEM_FAST_LAUNCH_SEG(OPV, 2);
+  if (g.nseg > 1) {
+    if constexpr (sizeof(T) == 4) {  // the segmented variants (z_segments): FP32 F and J^T
+      if (op == OP_RHS) {
+        SEM_FAST_EP_SEG(OP_RHS)
+      } else {
+        SEM_FAST_EP_SEG(OP_JACT)
+      }
     }
   } else if (op == OP_RHS) {
     SEM_FAST_EP(OP_RHS)
@@ -462,6 +470,8 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
   } else {
     SEM_FAST_EP(OP_JACT)
   }
+#undef SEM_FAST_EP_SEG
+#undef SEM_FAST_LAUNCH_SEG
 #undef SEM_FAST_EP
 #undef SEM_FAST_LAUNCH
   hipError_t e = hipGetLastError();
