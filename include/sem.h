@@ -16,8 +16,11 @@
  *         ndof = C * n_1 * n_2 * n_3 values per batch member.
  * Memory. Every pointer argument named u, v, w, f, jv, jtw, lam, ckpt, work is a DEVICE pointer
  *         owned by the caller, who keeps it alive until the stream work completes.  libsem
- *         never frees caller memory.  The context owns its tables and scratch (allocated in
- *         sem_setup, released in sem_destroy).
+ *         never frees caller memory.  The context owns its tables and scratch, released in
+ *         sem_destroy: the operators' tables and face buffer are allocated in sem_setup, the
+ *         time integrators' state buffers (twelve states) and captured step graphs at the first
+ *         call of an integrator entry point (so a context used for operator products only never
+ *         holds them).
  * Streams. All work is enqueued on the context stream (a hipStream_t passed as void*, NULL for
  *         the null stream) and returns without synchronising, except where documented.
  * Errors. Every function returns SEM_OK (0) or a negative sem_status and sets a thread-local
@@ -67,7 +70,8 @@ typedef struct sem_ctx_s* sem_ctx;
 
 /* Create a context: computes the GLL tables (Sec. 3.2: Legendre polynomials on GLL points,
    nodes, weights and the differentiation matrix D), the 1-D assembled lumped masses, and
-   allocates the scratch the operators and integrators need.  stream: hipStream_t or NULL. */
+   allocates the scratch the operators need (the integrators allocate theirs on first use).
+   stream: hipStream_t or NULL. */
 int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out);
 int sem_destroy(sem_ctx ctx);
 /* Rebind the stream used by later calls. */
