@@ -225,6 +225,31 @@ def test_full_size_3d(P, dtype):
     assert ef < tol and ej < tol and ev < tol
 
 
+def test_full_size_3d_trajectory(P):
+    # the 32^3 N=7 field through the fused RK4 stage kernels (every epilogue variant of the tuned
+    # 3-D kernel and its fixup) and the discrete adjoint, at the benchmark's step size
+    cfg = wl.C3
+    note("full-size 3-D 32^3 N=7 FP64: 3 RK4 steps + adjoint (checkpointed and stored stages)")
+    m = oracle.Mesh(3, cfg.N, list(cfg.E), list(cfg.L), cfg.nu)
+    c = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu)
+    xs = [m.coords(k) for k in range(3)]
+    u = wl.fourier_field(xs, cfg.L, wl.C3_K, wl.C3_SEEDS["u"])[None]
+    w = wl.normal_field(m.shape, wl.C3_SEEDS["w"])
+    dt, n, K = 1e-4, 3, 3
+    uT, ck = c.rk4_forward(gpu(u), dt, n, K)
+    lam = c.rk4_adjoint(ck, dt, n, K, gpu(w))
+    uT_ref, ck_ref = m.rk4_forward(u, dt, n, K)
+    lam_ref = m.rk4_adjoint(ck_ref, dt, n, K, w)
+    eu, el = rel(uT, uT_ref), rel(lam, lam_ref)
+    note(f"  errors u(T) {eu:.3e}  lambda_0 {el:.3e}")
+    assert eu < TOL_TRAJ and el < TOL_TRAJ
+    uS, st = c.rk_forward_stored(gpu(u), dt, n)
+    assert torch.equal(uS, uT)
+    c.set_adjoint_stages("store")
+    assert torch.equal(c.rk_adjoint_stored(st, dt, n, gpu(w)), c.rk4_adjoint(ck, dt, n, K, gpu(w)))
+    c.set_adjoint_stages("auto")
+
+
 # ------------------------------------------------------------------------------------------------
 # RK4 trajectories, adjoint and autograd
 # ------------------------------------------------------------------------------------------------
