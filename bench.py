@@ -98,6 +98,96 @@ def cpu_baseline(target_s=12.0):
                       f"{t_total:.1f} s total on {oracle.num_threads()} threads"}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_detail():
+    """The CPU oracle on the host in more detail: the 2-D single applies (median of 20) and one
+    3-D F + J^T pair on one thread and on all threads, and the C4 and C5 gradients extrapolated
+    from stated samples."""
+    import oracle
+
+    def med(fn, n):
+        ts = []
+        for _ in range(n):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    allt = oracle.num_threads()
+    out = {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "omp_threads_all": allt,
+           "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+    cfg = wl.C2
+    m2 = oracle.Mesh(2, cfg.N, list(cfg.E), list(cfg.L), cfg.nu)
+    xs = [m2.coords(k) for k in range(2)]
+    u2 = wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C2_SEEDS["u"])[None]
+    w2 = wl.normal_field(m2.shape, wl.C2_SEEDS["w"])
+    cfg3 = wl.C3
+    m3 = oracle.Mesh(3, cfg3.N, list(cfg3.E), list(cfg3.L), cfg3.nu)
+    xs3 = [m3.coords(k) for k in range(3)]
+    u3 = wl.fourier_field(xs3, cfg3.L, wl.C3_K, wl.C3_SEEDS["u"])[None]
+    w3 = wl.normal_field(m3.shape, wl.C3_SEEDS["w"])
+    try:
+        for label, nt in (("all_threads", 0), ("one_thread", 1)):
+            oracle.set_threads(nt)
+            f = med(lambda: m2.rhs(u2), 20)
+            jt = med(lambda: m2.jact_vec(u2, w2), 20)
+            t = time.perf_counter()
+            m3.rhs(u3)
+            m3.jact_vec(u3, w3)
+            t3 = time.perf_counter() - t
+            out[label] = {"threads": oracle.num_threads(),
+                          "c2_f_us": round(f * 1e6, 1), "c2_jt_us": round(jt * 1e6, 1),
+                          "c2_f_gdofs": round(m2.ndof / f / 1e9, 5), "c2_jt_gdofs": round(m2.ndof / jt / 1e9, 5),
+                          "c3_f_plus_jt_gdofs": round(m3.ndof / t3 / 1e9, 5), "c3_sample": "one F + J^T pair"}
+    finally:
+        oracle.set_threads(0)
+    del m3, u3, w3
+    # C4: one initial condition, 20 of the 500 steps, forward + adjoint; scaled to 500 steps
+    n4, k4 = 20, 10
+    u4 = wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C4_IC_SEED0)[None]
+    tg4 = wl.fourier_field(xs, cfg.L, wl.C2_K, wl.C4_TARGET_SEED0)[None]
+    t = time.perf_counter()
+    uT, ck = m2.rk4_forward(u4, wl.C4_DT, n4, k4)
+    m2.rk4_adjoint(ck, wl.C4_DT, n4, k4, uT - tg4)
+    t4 = (time.perf_counter() - t) * wl.C4_STEPS / n4
+    out["c4"] = {"gradients_per_s": round(1.0 / t4, 4),
+                 "sample": f"one IC, {n4} of {wl.C4_STEPS} steps (ckpt every {k4}) on all threads, "
+                           f"scaled by steps; the 64 ICs are independent, so gradients/s is per IC"}
+    # C5 plain loop: the first 8 problems, 10 steps, forward + adjoint; scaled by DOF and steps
+    probs = wl.c5_problems()
+    sub, n5, k5 = probs[:8], 10, 5
+    dof_sub, dof_all = 0, 0
+    t5 = 0.0
+    for i, p in enumerate(probs):
+        dof_all += 2 * (p.N * p.E) ** 2
+        if i >= len(sub):
+            continue
+        m = oracle.Mesh(2, p.N, [p.E, p.E], [1.0, 1.0], p.nu)
+        xp = [m.coords(k) for k in range(2)]
+        up = wl.fourier_field(xp, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]
+        tp = wl.fourier_field(xp, [1.0, 1.0], wl.C5_K, p.target_seed)[None]
+        t = time.perf_counter()
+        uT, ck = m.rk4_forward(up, p.dt, n5, k5)
+        m.rk4_adjoint(ck, p.dt, n5, k5, uT - tp)
+        t5 += time.perf_counter() - t
+        dof_sub += m.ndof
+    t_all = t5 * (dof_all / dof_sub) * (wl.C5_STEPS / n5)
+    out["c5_plain"] = {"gradients_per_s": round(len(probs) / t_all, 4),
+                       "sample": f"problems 0..{len(sub) - 1} ({dof_sub} of {dof_all} DOF), {n5} of {wl.C5_STEPS} "
+                                 f"steps, forward + adjoint on all threads, scaled by DOF and steps"}
+    return out
+
+
 def gradient_c4(P, nsteps=wl.C4_STEPS, K=wl.C4_CKPT):
     cfg = wl.C4
     ctx = P.Context(2, cfg.N, cfg.E, cfg.L, cfg.nu, batch=cfg.batch)
@@ -463,6 +553,7 @@ def main():
         log("lmvm done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_oracle"] = cpu_oracle_detail()
         log("cpu baseline done")
     print(json.dumps(out), flush=True)
 

@@ -52,6 +52,8 @@ def lib():
         _lib.orc_mass.argtypes = [pd, dp]
         _lib.orc_project_local.argtypes = [pd, dp, dp]
         _lib.orc_num_threads.argtypes = []
+        _lib.orc_set_threads.argtypes = [ctypes.c_int]
+        _lib.orc_set_threads.restype = None
     return _lib
 
 
@@ -225,3 +227,8 @@ def erk_tableau(scheme):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_threads(n):
+    """Threads of later oracle calls (n < 1: all the host offers)."""
+    lib().orc_set_threads(int(n))

@@ -865,3 +865,15 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of later parallel regions (n < 1: all).  Results do not depend on it: every summation
+   runs in a fixed order. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  static int all = 0;
+  if (!all) all = omp_get_max_threads();
+  omp_set_num_threads(n >= 1 ? n : all);
+#else
+  (void)n;
+#endif
+}
