@@ -140,6 +140,17 @@ def test_batched_fields(P, dim, N):
     assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < TOL_APPLY
 
 
+def test_batched_fields_fp32_segments(P):
+    # FP32 3-D with E_z >= 4: the z-segmented F and J^T kernels over a same-shape batch
+    note("same-shape batch fp32 3-D, z-segmented sweep")
+    m, c = make(P, 3, 7, [4, 2, 5], nu=0.02, batch=2, dtype=torch.float32)
+    u, v, w = fields(m, 13)
+    U, V, W = gpu(u, torch.float32), gpu(v, torch.float32), gpu(w, torch.float32)
+    assert rel(c.rhs(U), m.rhs(u)) < 1e-4
+    assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < 1e-4
+    assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < 1e-4
+
+
 # Wide element rows (5 and 8 wavefronts per workgroup) on domains stretched along x, so that the
 # elements stay near square.  On the unit square these meshes are so fine along x for nu = 0.02
 # that the operator's FP64 rounding floor (the oracle against an extended-precision evaluation)
