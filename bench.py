@@ -420,6 +420,27 @@ def lmvm_measure(P):
     return out
 
 
+def profile_case(P, case):
+    """A short, fixed workload for rocprofv3 kernel traces."""
+    if case == "c5_steps":
+        probs, specs = c5_sets(P)
+        B = P.Batch(specs)
+        B.autotune()
+        u = B.empty().normal_(0, 0.01)
+        for _ in range(3):
+            uT, ck = B.rk4_forward(u, 20, 10)
+            B.rk4_adjoint(ck, 20, 10, uT)
+    else:
+        cfg = wl.C3
+        ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
+        U, _, W = c3_inputs(ctx, torch.float64)
+        for scheme in ("rk4", "rk3"):
+            uT, ck = ctx.rk_forward(U, 1e-4, 10, 5, scheme=scheme)
+            ctx.rk_adjoint(ck, 1e-4, 10, 5, W, scheme=scheme)
+    torch.cuda.synchronize()
+    log(f"profile case {case} done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,12 +453,19 @@ def main():
                          "rk_adjoint, revolve, crank_nicolson, lmvm), or all")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain elementwise copy of one field (known bytes) for counter calibration")
+    ap.add_argument("--profile-case", choices=("c5_steps", "rk3d_steps"),
+                    help="run only a short workload for a profiler (no timing, no JSON contract): the "
+                         "batched set's RK4 steps and adjoint, or RK4 steps and adjoint on the 3-D field")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path runs on one MI355X, "
               "with no sharding or collectives", file=sys.stderr)
         sys.exit(2)
     import paper_1806_01422_amd as P
+
+    if args.profile_case:
+        profile_case(P, args.profile_case)
+        return
 
     cfg = wl.C3
     ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
