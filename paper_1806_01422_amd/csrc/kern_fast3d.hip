@@ -21,7 +21,8 @@
 // Direct-stiffness summation (Q^T).
 //   z: the last plane (c = 7) of an element is the first plane (c = 0) of the next one in the
 //      sweep; its partial sum is carried in registers, and the periodic wrap is closed after the
-//      sweep.  The input plane is carried too, so each step loads 7 new planes.
+//      sweep.  The input plane is carried too, so each step loads 7 new planes.  A sweep split
+//      into z-segments instead starts each segment by recomputing the layer before it.
 //   x: inside a workgroup the shared face of wavefronts w and w + 1 is added through LDS.
 //   workgroup faces: a workgroup owns the nodes x in [28X, 28X + 28), y in [7ey, 7ey + 7).  It
 //      writes its finished nodes to the output and, to a face buffer, its partial sums of the
@@ -403,9 +404,9 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   }
 }
 
-// z-segments per column: the FP32 F kernel (54 KB of LDS, at most 256 registers) fits two
-// workgroups per CU, which needs twice as many workgroups as CUs; every other variant holds one
-// workgroup per CU, where a segment would only add its recomputed layer.
+// z-segments per column: the FP32 F and J^T kernels (54 and 78 KB of LDS, at most 256 registers)
+// fit two workgroups per CU, which needs twice as many workgroups as CUs; every other variant
+// holds one workgroup per CU, where a segment would only add its recomputed layer.
 int z_segments(const ProbDev& hp, int op, bool f32) {
   return (f32 && (op == OP_RHS || op == OP_JACT) && hp.E[2] >= 4) ? 2 : 1;
 }
