@@ -8,8 +8,12 @@
 //                contributions, fixed order), the inverse assembled mass for F and J v, and a fused
 //                epilogue (plain store, or the RK4 stage / adjoint-stage updates).
 //
-// The element-local residual goes through a scratch array between the two kernels; the tuned
-// 3-D path (kern_fast3d.hip) sums inside the workgroup instead.
+//  persist2d_kernel : elem_kernel's work for a batched 2-D set of mixed orders as one persistent
+//                launch over a cost-sorted work list.
+//
+// The element-local residual goes through a scratch array between the element and summation
+// kernels; the tuned paths sum inside the workgroup instead (kern_fast2d.hip completely,
+// kern_fast3d.hip with a small face fixup).
 #include "sem_internal.h"
 
 namespace sem {
