@@ -906,3 +906,39 @@ def test_batch_launch_shapes_and_autotune(P):
     assert torch.equal(B.rhs(u), f0) and torch.equal(B.rk4_forward(u, 6, 0)[0], u1)
     with pytest.raises(P.SemError):
         B.configure(True, 0)
+
+
+# ------------------------------------------------------------------------------------------------
+# Resources: device memory across create / use / destroy cycles (last: a failure hides nothing)
+# ------------------------------------------------------------------------------------------------
+def test_lifecycle_releases_device_memory(P):
+    # contexts and batched sets with their integrator buffers, captured graphs, face buffers and
+    # autotuning, created and destroyed repeatedly: device memory returns to where it started
+    note("create / use / destroy cycles release their device memory")
+    specs, _ = batch_problems(6)
+
+    def cycle():
+        c = P.Context(3, 7, [8, 4, 4], [1.0, 1.0, 1.0], 0.01)
+        u = c.empty().normal_(0, 0.1)
+        uT, ck = c.rk4_forward(u, 1e-4, 2, 1)
+        c.rk4_adjoint(ck, 1e-4, 2, 1, uT)
+        c.rk_forward_stored(u, 1e-4, 2, scheme="rk3")
+        c.close()
+        B = P.Batch(specs)
+        B.autotune()
+        x = B.empty().normal_(0, 0.01)
+        xT, ckb = B.rk4_forward(x, 2, 1)
+        B.rk4_adjoint(ckb, 2, 1, xT)
+        B.close()
+
+    cycle()  # first use: library code objects, torch's allocator pools
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(4):
+        cycle()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free1 = torch.cuda.mem_get_info()[0]
+    note(f"  free before {free0 >> 20} MiB, after {free1 >> 20} MiB")
+    assert free0 - free1 < (64 << 20), (free0, free1)
