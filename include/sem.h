@@ -267,6 +267,8 @@ typedef struct sem_batch_s* sem_batch;
 /* dts: host array of count step sizes.  stream: hipStream_t or NULL. */
 int sem_batch_setup(const sem_desc* descs, const double* dts, int32_t count, void* stream, sem_batch* out);
 int sem_batch_destroy(sem_batch b);
+/* Rebind the stream used by later calls on the set (as sem_set_stream). */
+int sem_batch_set_stream(sem_batch b, void* stream);
 /* offsets: host array of count+1 entries (in values, not bytes); offsets[count] = total. */
 int sem_batch_query(sem_batch b, int64_t* offsets);
 /* F of every problem: f = F(u) on packed arrays. */

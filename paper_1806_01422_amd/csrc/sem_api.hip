@@ -1615,6 +1615,12 @@ int sem_batch_destroy(sem_batch b) {
   return SEM_OK;
 }
 
+int sem_batch_set_stream(sem_batch b, void* stream) {
+  if (!b) return fail(SEM_ERR_ARG, "null batch");
+  b->stream = static_cast<hipStream_t>(stream);
+  return SEM_OK;
+}
+
 int sem_batch_query(sem_batch b, int64_t* offsets) {
   if (!b || !offsets) return fail(SEM_ERR_ARG, "null argument");
   std::copy(b->offsets.begin(), b->offsets.end(), offsets);

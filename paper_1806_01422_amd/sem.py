@@ -118,6 +118,7 @@ _SIGS = {
     "sem_batch_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
     "sem_batch_set_adjoint_stages": [_vp, _i32],
     "sem_batch_configure": [_vp, _i32, _i32],
+    "sem_batch_set_stream": [_vp, _vp],
     "sem_batch_autotune": [_vp, ctypes.POINTER(_f64)],
 }
 EXPORTED = tuple(_SIGS)
@@ -564,6 +565,9 @@ class Batch:
         n = [e * q["order"] for e in q["elems"]]
         return packed[self.offsets[p]:self.offsets[p + 1]].view((1, q["dim"]) + tuple(reversed(n)))
 
+    def _bind(self):
+        _call(lib().sem_batch_set_stream(self._h, _stream()))
+
     def _chk(self, t, name):
         if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.dtype or not t.is_contiguous():
             raise SemError(f"{name} must be a contiguous CUDA tensor of dtype {self.dtype}")
@@ -574,12 +578,14 @@ class Batch:
     def rhs(self, u, out=None):
         self._chk(u, "u")
         out = self.empty() if out is None else self._chk(out, "out")
+        self._bind()
         _call(lib().sem_batch_rhs(self._h, _ptr(u), _ptr(out)))
         return out
 
     def jact_vec(self, u, w, out=None):
         self._chk(u, "u"), self._chk(w, "w")
         out = self.empty() if out is None else self._chk(out, "out")
+        self._bind()
         _call(lib().sem_batch_jact_vec(self._h, _ptr(u), _ptr(w), _ptr(out)))
         return out
 
@@ -589,6 +595,7 @@ class Batch:
         ck = None
         if ckpt_every:
             ck = torch.empty((nsteps // ckpt_every, self.total), dtype=self.dtype, device="cuda")
+        self._bind()
         _call(lib().sem_batch_rk4_forward(self._h, _ptr(u), int(nsteps), int(ckpt_every),
                                           _ptr(ck) if ck is not None else None))
         return u, ck
@@ -608,6 +615,7 @@ class Batch:
         self._chk(lamT, "lamT")
         lam = lamT.clone()
         work = self._work(ckpt_every, work)
+        self._bind()
         _call(lib().sem_batch_rk4_adjoint(self._h, _ptr(ckpt), int(nsteps), int(ckpt_every), _ptr(lam), _ptr(work)))
         return lam
 
@@ -618,6 +626,7 @@ class Batch:
         ck = None
         if ckpt_every:
             ck = torch.empty((nsteps // ckpt_every, self.total), dtype=self.dtype, device="cuda")
+        self._bind()
         _call(lib().sem_batch_rk_forward(self._h, code, _ptr(u), int(nsteps), int(ckpt_every),
                                          _ptr(ck) if ck is not None else None))
         return u, ck
@@ -627,6 +636,7 @@ class Batch:
         code = _scheme(scheme)
         lam = lamT.clone()
         work = self._work(ckpt_every, work)
+        self._bind()
         _call(lib().sem_batch_rk_adjoint(self._h, code, _ptr(ckpt), int(nsteps), int(ckpt_every), _ptr(lam),
                                          _ptr(work)))
         return lam
@@ -638,6 +648,7 @@ class Batch:
         u = u0.clone()
         S = 4 if code == _scheme("rk4") else 3
         st = torch.empty((nsteps, S, self.total), dtype=self.dtype, device="cuda")
+        self._bind()
         _call(lib().sem_batch_rk_forward_stored(self._h, code, _ptr(u), int(nsteps), _ptr(st)))
         return u, st
 
@@ -648,6 +659,7 @@ class Batch:
         if not stages.is_contiguous() or stages.dtype != self.dtype or stages.numel() != nsteps * S * self.total:
             raise SemError("stages must be the contiguous array rk_forward_stored returned")
         lam = lamT.clone()
+        self._bind()
         _call(lib().sem_batch_rk_adjoint_stored(self._h, code, _ptr(stages), int(nsteps), _ptr(lam)))
         return lam
 
@@ -659,5 +671,6 @@ class Batch:
     def autotune(self):
         """Time the candidate launch shapes on one RK4 step and keep the fastest; returns its ms."""
         ms = _f64()
+        self._bind()
         _call(lib().sem_batch_autotune(self._h, ctypes.byref(ms)))
         return ms.value

@@ -908,6 +908,31 @@ def test_batch_launch_shapes_and_autotune(P):
         B.configure(True, 0)
 
 
+def test_side_stream(P):
+    # contexts and batched sets follow torch's current stream: on a side stream (default
+    # priority), with torch producing the inputs and reading the outputs on that stream, the
+    # results equal the default stream's bitwise
+    note("operators and trajectories on a side stream")
+    m, c = make(P, 3, 7, [4, 1, 2])
+    u, _, w = fields(m, 5)
+    U = gpu(u)
+    f0, uT0 = c.rhs(U), c.rk4_forward(U, 1e-3, 4, 2)[0]
+    specs, _ = batch_problems(6)
+    B = P.Batch(specs)
+    x = gpu(wl.normal_field((B.total,), 9)) * 0.01
+    bf0, bT0 = B.rhs(x), B.rk4_forward(x, 3, 0)[0]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        U2, x2 = U * 1.0, x * 1.0
+        f1, uT1 = c.rhs(U2), c.rk4_forward(U2, 1e-3, 4, 2)[0]
+        bf1, bT1 = B.rhs(x2), B.rk4_forward(x2, 3, 0)[0]
+        d = torch.stack([(f1 - f0).abs().max(), (uT1 - uT0).abs().max(), (bf1 - bf0).abs().max(),
+                         (bT1 - bT0).abs().max()])
+    s.synchronize()
+    assert float(d.max()) == 0.0, d
+
+
 # ------------------------------------------------------------------------------------------------
 # Resources: device memory across create / use / destroy cycles (last: a failure hides nothing)
 # ------------------------------------------------------------------------------------------------
