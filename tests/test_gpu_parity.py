@@ -422,6 +422,23 @@ def test_c4_shape_batch_gradient(P):
     for b in (0, cfg.batch - 1):
         phi, g = m1.gradient(u0[b:b + 1], tg[b:b + 1], dt, n, K)
         assert rel(x.grad[b:b + 1], g) < TOL_TRAJ, b
+    # central finite differences of the whole-batch misfit along 16 seeded directions
+    note("  C4 shape: 16-direction central FD of the misfit")
+    U0, TG = gpu(u0), gpu(tg)
+
+    def phi_at(v):
+        yT, _ = c.rk4_forward(v, dt, n)
+        return float(0.5 * ((yT - TG) ** 2).sum())
+
+    eps = 1e-4
+    worst = 0.0
+    for j in range(16):
+        d = gpu(wl.normal_field(u0.shape, wl.C4_FD_SEED0 + j))
+        fd = (phi_at(U0 + eps * d) - phi_at(U0 - eps * d)) / (2 * eps)
+        ad = float((x.grad * d).sum())
+        worst = max(worst, abs(fd - ad) / abs(ad))
+    note(f"  worst relative FD error {worst:.2e}")
+    assert worst < 1e-6
 
 
 # ------------------------------------------------------------------------------------------------
