@@ -281,12 +281,14 @@ def gradient_c5(P, nsteps=wl.C5_STEPS, K=50):
 
     gb = batched()
     gp = plain()
-    diff = max(float((B.view(gb, i) - gp[i]).abs().max()) for i in range(len(probs)))
+    # a non-finite gradient anywhere makes the difference NaN (Python's max would skip it)
+    diff = float(torch.stack([(B.view(gb, i) - gp[i]).abs().max() for i in range(len(probs))]).max())
+    finite = bool(torch.isfinite(gb).all())
     tb = event_time_ms(batched, 1)
     tp = event_time_ms(plain, 1)
     return {"batched_gradients_per_s": round(len(probs) / (tb / 1e3), 2),
             "plain_gradients_per_s": round(len(probs) / (tp / 1e3), 2),
-            "batched_over_plain": round(tp / tb, 3), "max_abs_gradient_diff": diff,
+            "batched_over_plain": round(tp / tb, 3), "max_abs_gradient_diff": diff, "gradients_finite": finite,
             "problems": len(probs), "steps": nsteps, "total_dof": int(B.total),
             "autotuned_rk4_step_ms": round(step_ms, 4)}
 
