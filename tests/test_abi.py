@@ -72,5 +72,10 @@ def test_batched_problem_recipe():
     assert len(a) == 128 and a == b
     assert {p.E for p in a} <= set(wl.C5_E) and {p.N for p in a} <= set(wl.C5_N)
     assert all(1e-4 <= p.nu <= 1e-2 and p.dt > 0 for p in a)
+    # each step is inside its stability estimate, and the horizon ends at about half the time
+    # 1 / (2 pi K) ~ 0.04 in which the initial field's steepest mode (K = 4, max|u0| = 1) forms a shock
+    assert all(p.dt <= wl.stable_dt(2, p.N, p.E, 1.0, p.nu) for p in a)
+    assert all(p.dt * wl.C5_STEPS <= wl.C5_T_MAX * (1 + 1e-12) for p in a)
+    assert wl.C5_T_MAX < 0.6 / (2 * np.pi * wl.C5_K)
     # the 2-D 64x64 N=7 step of the adjoint configuration is inside the estimated stability region
     assert wl.C4_DT < wl.stable_dt(2, 7, 64, 1.0, 1e-3, safety=1.0)
