@@ -131,11 +131,11 @@ class BatchedProblem:
     target_seed: int
 
 
-C5_COUNT, C5_SEED, C5_STEPS, C5_ITERS, C5_ALPHA = 128, 40, 200, 20, 0.5
+C5_COUNT, C5_SEED, C5_STEPS = 128, 40, 200
 C5_E = (8, 16, 32, 64)
 C5_N = (5, 7, 9)
 C5_K = 4
-# Horizon cap of the batched set: 200 steps end by T = 0.02, half the time 1 / (2 pi K max|u0|)
+# Horizon cap of the batched set: 200 steps end by T = 0.02, about half the time 1 / (2 pi K max|u0|)
 # ~ 0.04 in which the steepest mode of the initial field (K = 4, max|u0| = 1) turns into a shock
 # the meshes cannot resolve at the low viscosities of the set.
 C5_T_MAX = 0.02
