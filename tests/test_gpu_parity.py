@@ -520,6 +520,17 @@ def test_c5_full_set_sampled(P):
         a0, aT = float(B.view(u, i).abs().max()), float(B.view(uT, i).abs().max())
         assert aT <= 1.5 * a0, (i, a0, aT)
     assert bool(torch.isfinite(lam).all())
+    # full-horizon parity on the least viscous problem of each order among the meshes of at most
+    # 16^2 elements (the oracle finishes those 200 steps in seconds)
+    for N in sorted({p.N for p in probs}):
+        i = min((i for i, p in enumerate(probs) if p.N == N and p.E <= 16), key=lambda i: probs[i].nu)
+        m, p = meshes[i], probs[i]
+        ui, ti = B.view(u, i).cpu().numpy(), B.view(tg, i).cpu().numpy()
+        ref, ckr = m.rk4_forward(ui, p.dt, wl.C5_STEPS, 50)
+        errs = (rel(B.view(uT, i), ref), rel(B.view(lam, i), m.rk4_adjoint(ckr, p.dt, wl.C5_STEPS, 50, ref - ti)))
+        note(f"  problem {i}: N={p.N} E={p.E} nu={p.nu:.2e}, {wl.C5_STEPS} steps: u(T) {errs[0]:.2e}  "
+             f"lambda_0 {errs[1]:.2e}")
+        assert errs[0] < TOL_TRAJ and errs[1] < TOL_TRAJ, i
 
 
 def test_batch_tuned_problems(P):
