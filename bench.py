@@ -432,6 +432,8 @@ def profile_case(P, case):
         for _ in range(3):
             uT, ck = B.rk4_forward(u, 20, 10)
             B.rk4_adjoint(ck, 20, 10, uT)
+    elif case == "c4_gradient":
+        gradient_c4(P, nsteps=100)
     else:
         cfg = wl.C3
         ctx = P.Context(3, cfg.N, cfg.E, cfg.L, cfg.nu, dtype=torch.float64)
@@ -455,9 +457,10 @@ def main():
                          "rk_adjoint, revolve, crank_nicolson, lmvm), or all")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain elementwise copy of one field (known bytes) for counter calibration")
-    ap.add_argument("--profile-case", choices=("c5_steps", "rk3d_steps"),
-                    help="run only a short workload for a profiler (no timing, no JSON contract): the "
-                         "batched set's RK4 steps and adjoint, or RK4 steps and adjoint on the 3-D field")
+    ap.add_argument("--profile-case", choices=("c5_steps", "c4_gradient", "rk3d_steps"),
+                    help="run only a short workload for a profiler (no JSON contract): the batched set's "
+                         "RK4 steps and adjoint, the 64-IC misfit gradient over 100 steps (warm-up plus "
+                         "one timed gradient), or RK4 steps and adjoint on the 3-D field")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path runs on one MI355X, "
