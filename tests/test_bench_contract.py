@@ -1,7 +1,9 @@
 """Host-side checks of bench.py's reporting: the traffic figure is only reported while the
-counter summary matches the kernel source it was measured on."""
+counter summary matches the kernel source it was measured on, and a request for several GPUs is
+refused."""
 import hashlib
 import os
+import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -34,3 +36,11 @@ def test_traffic_is_null_for_a_changed_kernel(tmp_path, monkeypatch):
 def test_traffic_is_null_without_summary(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.md"))
     assert bench.measured_traffic() is None
+
+
+def test_more_than_one_gpu_is_refused():
+    # the benchmark measures one GPU; asking for more ends with a message before any GPU work
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
