@@ -456,30 +456,48 @@ class SEMRhs(torch.autograd.Function):
 class SEMTrajectory(torch.autograd.Function):
     """u(T) = Phi_dt^nsteps(u_0) for a time integrator ("rk4", "rk3" or Crank-Nicolson "cn"), with
     backward by the discrete adjoint of that scheme (Sec. 4.1) from uniform checkpoints every
-    ckpt_every steps, recomputed segment by segment (Sec. 5.3)."""
+    ckpt_every steps, recomputed segment by segment (Sec. 5.3).
+
+    stored_tail > 0 (Runge-Kutta only): the forward sweep keeps every stage state of its last
+    stored_tail segments, so the backward runs their adjoint from those states (J^T only) and
+    recomputes only the segments before them, at stored_tail * ckpt_every * S extra states."""
 
     @staticmethod
-    def forward(ctx, u0, sem, dt, nsteps, ckpt_every, scheme="rk4"):
+    def forward(ctx, u0, sem, dt, nsteps, ckpt_every, scheme="rk4", stored_tail=0):
+        n_tail = stored_tail * ckpt_every if scheme != "cn" else 0
+        if n_tail < 0 or n_tail > nsteps:
+            raise SemError(f"stored_tail * ckpt_every = {n_tail} must lie in [0, nsteps = {nsteps}]")
+        n_head = nsteps - n_tail
+        st = None
         if scheme == "cn":
             uT, ck, _ = sem.cn_forward(u0.contiguous(), dt, nsteps, ckpt_every)
         else:
-            uT, ck = sem.rk_forward(u0.contiguous(), dt, nsteps, ckpt_every, scheme=scheme)
-        ctx.sem, ctx.dt, ctx.nsteps, ctx.K, ctx.scheme = sem, dt, nsteps, ckpt_every, scheme
-        ctx.save_for_backward(ck)
+            uT, ck = u0.contiguous(), None
+            if n_head or not n_tail:
+                uT, ck = sem.rk_forward(uT, dt, n_head, ckpt_every, scheme=scheme)
+            if n_tail:
+                uT, st = sem.rk_forward_stored(uT, dt, n_tail, scheme=scheme)
+        ctx.sem, ctx.dt, ctx.K, ctx.scheme = sem, dt, ckpt_every, scheme
+        ctx.n_head, ctx.n_tail = n_head, n_tail
+        ctx.save_for_backward(ck, st)
         return uT
 
     @staticmethod
     def backward(ctx, g):
-        (ck,) = ctx.saved_tensors
+        ck, st = ctx.saved_tensors
         if ctx.scheme == "cn":
-            lam0, _ = ctx.sem.cn_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous())
+            lam0, _ = ctx.sem.cn_adjoint(ck, ctx.dt, ctx.n_head, ctx.K, g.contiguous())
         else:
-            lam0 = ctx.sem.rk_adjoint(ck, ctx.dt, ctx.nsteps, ctx.K, g.contiguous(), scheme=ctx.scheme)
-        return lam0, None, None, None, None, None
+            lam0 = g.contiguous()
+            if ctx.n_tail:
+                lam0 = ctx.sem.rk_adjoint_stored(st, ctx.dt, ctx.n_tail, lam0, scheme=ctx.scheme)
+            if ctx.n_head or not ctx.n_tail:
+                lam0 = ctx.sem.rk_adjoint(ck, ctx.dt, ctx.n_head, ctx.K, lam0, scheme=ctx.scheme)
+        return lam0, None, None, None, None, None, None
 
 
-def trajectory(u0, sem, dt, nsteps, ckpt_every, scheme="rk4"):
-    return SEMTrajectory.apply(u0, sem, dt, nsteps, ckpt_every, scheme)
+def trajectory(u0, sem, dt, nsteps, ckpt_every, scheme="rk4", stored_tail=0):
+    return SEMTrajectory.apply(u0, sem, dt, nsteps, ckpt_every, scheme, stored_tail)
 
 
 class SEMTrajectoryRevolve(torch.autograd.Function):

@@ -304,6 +304,31 @@ def test_c1_trajectory_and_gradient(P):
         assert abs(fd - ad) <= 1e-6 * abs(ad), (s, fd, ad)
 
 
+@pytest.mark.parametrize("scheme", ["rk4", "rk3"])
+def test_trajectory_stored_tail(P, scheme):
+    # the last stored_tail segments keep their stage states in the forward sweep: the same values
+    # as the checkpointed sweep (the same launches on the same states), and the oracle's gradient
+    note(f"trajectory with stored tail segments ({scheme}), 2-D 8x3 N=7, batch 2")
+    m, c = make(P, 2, 7, [8, 3], nu=0.01, batch=2)
+    u, _, w = fields(m, 23)
+    dt, n, K = 2e-3, 20, 5
+    ref = None
+    for tail in (0, 1, 3, 4):
+        x = gpu(u).requires_grad_(True)
+        yT = P.trajectory(x, c, dt, n, K, scheme=scheme, stored_tail=tail)
+        (yT * gpu(w)).sum().backward()
+        if ref is None:
+            ref = (yT.detach().clone(), x.grad.clone())
+            if scheme == "rk4":
+                uT_ref, ck_ref = m.rk4_forward(u, dt, n, K)
+                assert rel(yT, uT_ref) < TOL_TRAJ
+                assert rel(x.grad, m.rk4_adjoint(ck_ref, dt, n, K, w)) < TOL_TRAJ
+        else:
+            assert torch.equal(yT, ref[0]) and torch.equal(x.grad, ref[1]), tail
+    with pytest.raises(P.SemError):
+        P.trajectory(gpu(u).requires_grad_(True), c, dt, n, K, scheme=scheme, stored_tail=5)
+
+
 @pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1),
                                            (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2),
                                            (2, 7, [8, 3], 2), (2, 7, [8, 1], 1), (2, 5, [8, 2], 2)])
