@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E datasheet peak
-C4_STORED_TAIL = 3  # segments of the 64-IC gradient whose stage states the forward sweep keeps
+C4_TAIL_RESERVE = 80e9  # HBM left free beside the stored segments (segment recompute storage, fields)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fast3d_jact_32cube_n7.md")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_01422_amd", "csrc", f) for f in ("kern_fast3d.hip", "fast_common.h")]
 
@@ -569,11 +569,14 @@ def main():
     if want("c4_adjoint"):
         gps, ms = gradient_c4(P)
         torch.cuda.empty_cache()
-        # the last 3 of the 10 segments kept whole: 150 steps x 4 states x 205.5 MB = 123 GB of HBM
-        gps_t, ms_t = gradient_c4(P, stored_tail=C4_STORED_TAIL)
+        # as many of the last segments kept whole as free HBM holds beside the reserve: one segment
+        # is 50 steps x 4 states x 205.5 MB = 41.1 GB (4 segments on an idle 288 GB MI355X)
+        seg_bytes = wl.C4_CKPT * 4 * 8 * 401408 * wl.C4.batch
+        tail = int(max(0, min(wl.C4_STEPS // wl.C4_CKPT, (torch.cuda.mem_get_info()[0] - C4_TAIL_RESERVE) // seg_bytes)))
+        gps_t, ms_t = gradient_c4(P, stored_tail=tail)
         out["c4_adjoint"] = {"gradients_per_s": round(gps, 3), "ms_per_batch_of_64": round(ms, 2),
                              "steps": wl.C4_STEPS, "ckpt_every": wl.C4_CKPT,
-                             "stored_tail_segments": C4_STORED_TAIL,
+                             "stored_tail_segments": tail, "stored_tail_bytes": tail * seg_bytes,
                              "gradients_per_s_stored_tail": round(gps_t, 3),
                              "ms_per_batch_of_64_stored_tail": round(ms_t, 2),
                              "workload": "2-D 64x64 N=7, 64 ICs, RK4 dt=2e-4, misfit gradient via autograd"}
