@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 import workloads as wl  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E datasheet peak
-C4_TAIL_RESERVE = 80e9  # HBM left free beside the stored segments (segment recompute storage, fields)
+HBM_RESERVE = 80e9  # HBM left free beside stored stage states (segment recompute storage, fields)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fast3d_jact_32cube_n7.md")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1806_01422_amd", "csrc", f) for f in ("kern_fast3d.hip", "fast_common.h")]
 
@@ -290,11 +290,31 @@ def gradient_c5(P, nsteps=wl.C5_STEPS, K=50):
     finite = bool(torch.isfinite(gb).all())
     tb = event_time_ms(batched, 1)
     tp = event_time_ms(plain, 1)
-    return {"batched_gradients_per_s": round(len(probs) / (tb / 1e3), 2),
-            "plain_gradients_per_s": round(len(probs) / (tp / 1e3), 2),
-            "batched_over_plain": round(tp / tb, 3), "max_abs_gradient_diff": diff, "gradients_finite": finite,
-            "problems": len(probs), "steps": nsteps, "total_dof": int(B.total),
-            "autotuned_rk4_step_ms": round(step_ms, 4)}
+    out = {"batched_gradients_per_s": round(len(probs) / (tb / 1e3), 2),
+           "plain_gradients_per_s": round(len(probs) / (tp / 1e3), 2),
+           "batched_over_plain": round(tp / tb, 3), "max_abs_gradient_diff": diff, "gradients_finite": finite,
+           "problems": len(probs), "steps": nsteps, "total_dof": int(B.total),
+           "autotuned_rk4_step_ms": round(step_ms, 4)}
+    for c in ctxs:
+        c.close()
+    del gp, views
+    torch.cuda.empty_cache()
+
+    # every stage state of all steps kept by the forward sweep (4 states per step), when free HBM
+    # holds them beside the same reserve as the 64-IC gradient: the adjoint then recomputes nothing
+    st_bytes = nsteps * 4 * 8 * int(B.total)
+    if torch.cuda.mem_get_info()[0] - HBM_RESERVE >= st_bytes:
+        def batched_stored():
+            uT, st = B.rk_forward_stored(u0, nsteps)
+            return B.rk_adjoint_stored(st, nsteps, uT - tg)
+
+        gs = batched_stored()
+        ts = event_time_ms(batched_stored, 1)
+        out.update({"all_stages_stored_gradients_per_s": round(len(probs) / (ts / 1e3), 2),
+                    "all_stages_stored_bytes": st_bytes,
+                    "all_stages_stored_max_abs_gradient_diff": float((gs - gb).abs().max())})
+    B.close()
+    return out
 
 
 def rk_adjoint_ratio(P, nsteps=10):
@@ -572,7 +592,7 @@ def main():
         # as many of the last segments kept whole as free HBM holds beside the reserve: one segment
         # is 50 steps x 4 states x 205.5 MB = 41.1 GB (4 segments on an idle 288 GB MI355X)
         seg_bytes = wl.C4_CKPT * 4 * 8 * 401408 * wl.C4.batch
-        tail = int(max(0, min(wl.C4_STEPS // wl.C4_CKPT, (torch.cuda.mem_get_info()[0] - C4_TAIL_RESERVE) // seg_bytes)))
+        tail = int(max(0, min(wl.C4_STEPS // wl.C4_CKPT, (torch.cuda.mem_get_info()[0] - HBM_RESERVE) // seg_bytes)))
         gps_t, ms_t = gradient_c4(P, stored_tail=tail)
         out["c4_adjoint"] = {"gradients_per_s": round(gps, 3), "ms_per_batch_of_64": round(ms, 2),
                              "steps": wl.C4_STEPS, "ckpt_every": wl.C4_CKPT,
