@@ -206,10 +206,10 @@ def gradient_c4(P, nsteps=wl.C4_STEPS, K=wl.C4_CKPT, stored_tail=0):
         loss.backward()
         return x.grad
 
-    grad()  # warm-up (graph capture, allocations)
+    g = grad()  # warm-up (graph capture, allocations); its gradient is returned
     ms = event_time_ms(grad, 1)
     ctx.close()
-    return cfg.batch / (ms / 1e3), ms
+    return cfg.batch / (ms / 1e3), ms, g
 
 
 def apply_2d(P):
@@ -587,18 +587,19 @@ def main():
         out["c2_apply"] = apply_2d(P)
         log("2-D apply done")
     if want("c4_adjoint"):
-        gps, ms = gradient_c4(P)
+        gps, ms, g_plain = gradient_c4(P)
         torch.cuda.empty_cache()
         # as many of the last segments kept whole as free HBM holds beside the reserve: one segment
         # is 50 steps x 4 states x 205.5 MB = 41.1 GB (4 segments on an idle 288 GB MI355X)
         seg_bytes = wl.C4_CKPT * 4 * 8 * 401408 * wl.C4.batch
         tail = int(max(0, min(wl.C4_STEPS // wl.C4_CKPT, (torch.cuda.mem_get_info()[0] - HBM_RESERVE) // seg_bytes)))
-        gps_t, ms_t = gradient_c4(P, stored_tail=tail)
+        gps_t, ms_t, g_tail = gradient_c4(P, stored_tail=tail)
         out["c4_adjoint"] = {"gradients_per_s": round(gps, 3), "ms_per_batch_of_64": round(ms, 2),
                              "steps": wl.C4_STEPS, "ckpt_every": wl.C4_CKPT,
                              "stored_tail_segments": tail, "stored_tail_bytes": tail * seg_bytes,
                              "gradients_per_s_stored_tail": round(gps_t, 3),
                              "ms_per_batch_of_64_stored_tail": round(ms_t, 2),
+                             "stored_tail_max_abs_gradient_diff": float((g_tail - g_plain).abs().max()),
                              "workload": "2-D 64x64 N=7, 64 ICs, RK4 dt=2e-4, misfit gradient via autograd"}
         torch.cuda.empty_cache()
         log("c4 done")

@@ -73,8 +73,12 @@ typedef struct sem_ctx_s* sem_ctx;
    allocates the scratch the operators need (the integrators allocate theirs on first use).
    stream: hipStream_t or NULL. */
 int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out);
+/* Waits for the context's work (on its current stream, which carries the work of every stream
+   it used before: see sem_set_stream), then frees its tables, scratch and graphs. */
 int sem_destroy(sem_ctx ctx);
-/* Rebind the stream used by later calls. */
+/* Rebind the stream used by later calls.  The new stream first waits (a device-side event wait,
+   no host synchronisation) for everything already enqueued on the old one: the context's scratch
+   and graphs are shared by all its calls, so its work stays one ordered chain. */
 int sem_set_stream(sem_ctx ctx, void* stream);
 /* ndof per batch member (C * nodes) and unique nodes per component. Either pointer may be NULL. */
 int sem_query(sem_ctx ctx, int64_t* ndof, int64_t* nodes);
@@ -266,8 +270,10 @@ const char* sem_last_error(void);
 typedef struct sem_batch_s* sem_batch;
 /* dts: host array of count step sizes.  stream: hipStream_t or NULL. */
 int sem_batch_setup(const sem_desc* descs, const double* dts, int32_t count, void* stream, sem_batch* out);
+/* Waits for the set's work (as sem_destroy), then frees it. */
 int sem_batch_destroy(sem_batch b);
-/* Rebind the stream used by later calls on the set (as sem_set_stream). */
+/* Rebind the stream used by later calls on the set (as sem_set_stream: the new stream waits for
+   the old one's work). */
 int sem_batch_set_stream(sem_batch b, void* stream);
 /* offsets: host array of count+1 entries (in values, not bytes); offsets[count] = total. */
 int sem_batch_query(sem_batch b, int64_t* offsets);
@@ -296,7 +302,8 @@ int sem_batch_set_adjoint_stages(sem_batch b, int32_t mode);
    (2-D sets of more than one problem) with `param` workgroups walking a cost-sorted work list;
    persistent = 0: one launch per order class with `param` elements per workgroup (0 = default;
    orders without that choice keep their default).  Drops the captured RK4 graphs (recaptured on
-   the next integration). */
+   the next integration); when graphs exist it first synchronises the set's stream, so that no
+   graph launch is still in flight when its executable is destroyed. */
 int sem_batch_configure(sem_batch b, int32_t persistent, int32_t param);
 /* Time the candidate launch shapes on the captured RK4 step of this problem set and keep the
    fastest (synchronises the stream; overwrites the integrator's internal state buffers, not

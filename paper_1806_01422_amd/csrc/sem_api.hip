@@ -429,13 +429,19 @@ struct Integrator {
   int64_t work_states(int32_t K) const { return (int64_t)K * (stores_stages() ? MAX_STAGE_STATES : 1); }
 
   ~Integrator() {
-    reset_graphs();
+    reset_graphs(nullptr);
     if (cap) (void)hipStreamDestroy(cap);
   }
   void* b(int i) { return buf[i].p; }
 
-  // drop the captured graphs (after the operator's launch configuration changed)
-  void reset_graphs() {
+  // Drop the captured graphs (after the operator's launch configuration changed).  Graph launches
+  // may still be in flight on the handle's stream s (every earlier stream of the handle is
+  // chained into it), so s is synchronised before any executable graph is destroyed; null s: the
+  // caller has already waited (the handle's destroy).
+  void reset_graphs(hipStream_t s, bool wait = false) {
+    bool any = false;
+    for (int k = 0; k < NSCHEME; ++k) any = any || gstep[k] || gadj[k];
+    if (any && wait) (void)hipStreamSynchronize(s);
     for (int k = 0; k < NSCHEME; ++k) {
       if (gstep[k]) (void)hipGraphExecDestroy(gstep[k]);
       if (gadj[k]) (void)hipGraphExecDestroy(gadj[k]);
@@ -1150,6 +1156,7 @@ struct Lmvm {
 struct sem_ctx_s {
   sem_desc d{};
   hipStream_t stream = nullptr;
+  hipEvent_t chain = nullptr;  // orders work across a change of stream (chain_streams)
   OpSet os;
   Integrator integ;
   int64_t ndof = 0, nodes = 0;
@@ -1163,9 +1170,24 @@ struct sem_batch_s {
   std::vector<double> dts;
   std::vector<int64_t> offsets;
   hipStream_t stream = nullptr;
+  hipEvent_t chain = nullptr;
   OpSet os;
   Integrator integ;
 };
+
+namespace {
+// A handle's internal buffers and graphs are shared by all of its calls, so its work must form
+// one ordered chain even when the caller moves it to another stream: the new stream first waits
+// for everything already enqueued on the old one.  Synchronising the current stream then also
+// waits for the work of every stream the handle used before.
+int chain_streams(hipStream_t from, hipStream_t to, hipEvent_t& ev) {
+  if (from == to) return SEM_OK;
+  if (!ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ev, from));
+  HIPCHK(hipStreamWaitEvent(to, ev, 0));
+  return SEM_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -1200,15 +1222,19 @@ int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out) {
 
 int sem_destroy(sem_ctx c) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
+  // the current stream carries the handle's whole chain of work (chain_streams)
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  if (c->chain) (void)hipEventDestroy(c->chain);
   delete c;
   return SEM_OK;
 }
 
 int sem_set_stream(sem_ctx c, void* stream) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
-  c->stream = static_cast<hipStream_t>(stream);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int rc = chain_streams(c->stream, s, c->chain)) return rc;
+  c->stream = s;
   return SEM_OK;
 }
 
@@ -1611,13 +1637,16 @@ int sem_batch_destroy(sem_batch b) {
   if (!b) return fail(SEM_ERR_ARG, "null batch");
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   else (void)hipDeviceSynchronize();
+  if (b->chain) (void)hipEventDestroy(b->chain);
   delete b;
   return SEM_OK;
 }
 
 int sem_batch_set_stream(sem_batch b, void* stream) {
   if (!b) return fail(SEM_ERR_ARG, "null batch");
-  b->stream = static_cast<hipStream_t>(stream);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int rc = chain_streams(b->stream, s, b->chain)) return rc;
+  b->stream = s;
   return SEM_OK;
 }
 
@@ -1736,7 +1765,7 @@ int sem_batch_configure(sem_batch b, int32_t persistent, int32_t param) {
     }
     os.persistent = 0;
   }
-  b->integ.reset_graphs();
+  b->integ.reset_graphs(b->stream, true);
   return SEM_OK;
 }
 

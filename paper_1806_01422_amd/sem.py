@@ -464,7 +464,10 @@ class SEMTrajectory(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, u0, sem, dt, nsteps, ckpt_every, scheme="rk4", stored_tail=0):
-        n_tail = stored_tail * ckpt_every if scheme != "cn" else 0
+        if scheme == "cn" and stored_tail:
+            raise SemError("stored_tail applies to the Runge-Kutta schemes only; the Crank-Nicolson "
+                           "adjoint always recomputes from its checkpoints")
+        n_tail = stored_tail * ckpt_every
         if n_tail < 0 or n_tail > nsteps:
             raise SemError(f"stored_tail * ckpt_every = {n_tail} must lie in [0, nsteps = {nsteps}]")
         n_head = nsteps - n_tail
