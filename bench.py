@@ -252,67 +252,118 @@ def c5_sets(P):
     return probs, specs
 
 
-def gradient_c5(P, nsteps=wl.C5_STEPS, K=50):
-    """One gradient-descent iteration (forward + adjoint gradient of all 128 problems), batched
-    (packed set, one launch per order class per stage, graph-captured steps) vs plain (one context
-    per problem, launched one after another).  Both paths run the same kernels, so the gradients
-    are identical."""
+def gradient_c5(P, nsteps=wl.C5_STEPS, K=50, iters=wl.C5_ITERS, alpha=wl.C5_ALPHA, plain_iters=2):
+    """Gradient descent on the initial conditions of all 128 problems: `iters` iterations of
+    u0 <- u0 - alpha d / max|d| per problem, d = W g, g the misfit gradient (forward + adjoint over
+    `nsteps` RK4 steps, checkpoint every K) and W = M / mean(M).  Batched: the packed set (autotuned
+    launches, graph-captured steps).  Plain: one context per problem, launched one after another;
+    it runs `plain_iters` iterations (the cost of an iteration does not depend on the iterate) and
+    its iterate there is compared with the batched loop's, value by value.  Both run the same
+    kernels and the same elementwise update, so the iterates are bitwise equal."""
     probs, specs = c5_sets(P)
     B = P.Batch(specs)
     step_ms = B.autotune()  # launch shape chosen by timing the captured RK4 step
     u0 = B.empty()
     tg = B.empty()
+    nodes = []
     for i, p in enumerate(probs):
         ctxi = P.Context(2, p.N, (p.E, p.E), (1.0, 1.0), p.nu)
         xs = [ctxi.node_coords(k) for k in range(2)]
         B.view(u0, i).copy_(torch.from_numpy(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]))
         B.view(tg, i).copy_(torch.from_numpy(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.target_seed)[None]))
+        nodes.append(ctxi.nodes)
         ctxi.close()
+    # W = M / mean(M): on the unit square mean(M) = 1 / nodes
+    wB = B.mass()
+    for i in range(len(probs)):
+        B.view(wB, i).mul_(float(nodes[i]))
 
-    def batched():
+    sizes = torch.tensor([int(B.offsets[i + 1] - B.offsets[i]) for i in range(len(probs))], device="cuda")
+
+    def step(u, g, w, views=None):
+        # views: the packed set's problem slices (one scale per problem), else one problem
+        d = w * g
+        if views is None:
+            scale = alpha / d.abs().max()
+        else:
+            mx = torch.stack([views(d, i).abs().max() for i in range(len(probs))])
+            scale = torch.repeat_interleave(alpha / mx, sizes)
+        d.mul_(scale)
+        u.sub_(d)
+
+    def batched_loop(n_it, record=None):
+        u = u0.clone()
+        for it in range(n_it):
+            uT, ck = B.rk4_forward(u, nsteps, K)
+            r = uT - tg
+            if record is not None:
+                record.append(0.5 * (r * r).sum())
+            g = B.rk4_adjoint(ck, nsteps, K, r)
+            step(u, g, wB, B.view)
+        return u
+
+    ctxs = [P.Context(2, p.N, (p.E, p.E), (1.0, 1.0), p.nu) for p in probs]
+    wps = [c.mass() * float(n) for c, n in zip(ctxs, nodes)]
+    views = [(B.view(u0, i).contiguous(), B.view(tg, i).contiguous()) for i in range(len(probs))]
+
+    def plain_loop(n_it):
+        us = [ui.clone() for ui, _ in views]
+        for it in range(n_it):
+            for c, p, u, (_, ti), w in zip(ctxs, probs, us, views, wps):
+                uT, ck = c.rk4_forward(u, p.dt, nsteps, K)
+                g = c.rk4_adjoint(ck, p.dt, nsteps, K, uT - ti)
+                step(u, g, w)
+        return us
+
+    phis = []
+    ub = batched_loop(iters, phis)  # warm-up and the objective history
+    phis = [float(v) for v in phis]
+    finite = bool(torch.isfinite(ub).all())
+    ub2 = batched_loop(plain_iters)
+    up2 = plain_loop(plain_iters)
+    # a non-finite value anywhere makes the difference NaN (Python's max would skip it)
+    diff = float(torch.stack([(B.view(ub2, i) - up2[i]).abs().max() for i in range(len(probs))]).max())
+    tb = event_time_ms(lambda: batched_loop(iters), 1, warmup=0)
+    tp = event_time_ms(lambda: plain_loop(plain_iters), 1, warmup=0)
+    ng_b, ng_p = len(probs) * iters, len(probs) * plain_iters
+    out = {"workload": f"{len(probs)} uneven 2-D problems, {iters} gradient-descent iterations on the initial "
+                       f"conditions, {nsteps} RK4 steps each (checkpoint every {K}); mass-weighted direction, step normalised to "
+                       f"max change {alpha} per problem and iteration",
+           "batched_gradients_per_s": round(ng_b / (tb / 1e3), 2),
+           "plain_gradients_per_s": round(ng_p / (tp / 1e3), 2),
+           "batched_over_plain": round((tp / ng_p) / (tb / ng_b), 3),
+           "batched_loop_s": round(tb / 1e3, 3), "plain_iterations_timed": plain_iters,
+           "max_abs_iterate_diff_after_plain_iterations": diff, "iterates_finite": finite,
+           "objective_first_last": [round(phis[0], 6), round(phis[-1], 6)],
+           "objective_decreased_every_iteration": all(b < a for a, b in zip(phis, phis[1:])),
+           "problems": len(probs), "total_dof": int(B.total), "autotuned_rk4_step_ms": round(step_ms, 4)}
+    for c in ctxs:
+        c.close()
+    del up2, views, wps
+    torch.cuda.empty_cache()
+
+    # one gradient with every stage state of all steps kept by the forward sweep (4 states per
+    # step), when free HBM holds them beside the same reserve as the 64-IC gradient: the adjoint
+    # then recomputes nothing
+    def batched_grad():
         uT, ck = B.rk4_forward(u0, nsteps, K)
         return B.rk4_adjoint(ck, nsteps, K, uT - tg)
 
-    ctxs = [P.Context(2, p.N, (p.E, p.E), (1.0, 1.0), p.nu) for p in probs]
-    views = [(B.view(u0, i).contiguous(), B.view(tg, i).contiguous()) for i in range(len(probs))]
-
-    def plain():
-        out = []
-        for c, p, (ui, ti) in zip(ctxs, probs, views):
-            uT, ck = c.rk4_forward(ui, p.dt, nsteps, K)
-            out.append(c.rk4_adjoint(ck, p.dt, nsteps, K, uT - ti))
-        return out
-
-    gb = batched()
-    gp = plain()
-    # a non-finite gradient anywhere makes the difference NaN (Python's max would skip it)
-    diff = float(torch.stack([(B.view(gb, i) - gp[i]).abs().max() for i in range(len(probs))]).max())
-    finite = bool(torch.isfinite(gb).all())
-    tb = event_time_ms(batched, 1)
-    tp = event_time_ms(plain, 1)
-    out = {"batched_gradients_per_s": round(len(probs) / (tb / 1e3), 2),
-           "plain_gradients_per_s": round(len(probs) / (tp / 1e3), 2),
-           "batched_over_plain": round(tp / tb, 3), "max_abs_gradient_diff": diff, "gradients_finite": finite,
-           "problems": len(probs), "steps": nsteps, "total_dof": int(B.total),
-           "autotuned_rk4_step_ms": round(step_ms, 4)}
-    for c in ctxs:
-        c.close()
-    del gp, views
-    torch.cuda.empty_cache()
-
-    # every stage state of all steps kept by the forward sweep (4 states per step), when free HBM
-    # holds them beside the same reserve as the 64-IC gradient: the adjoint then recomputes nothing
     st_bytes = nsteps * 4 * 8 * int(B.total)
     if torch.cuda.mem_get_info()[0] - HBM_RESERVE >= st_bytes:
         def batched_stored():
             uT, st = B.rk_forward_stored(u0, nsteps)
             return B.rk_adjoint_stored(st, nsteps, uT - tg)
 
+        gb = batched_grad()
         gs = batched_stored()
+        tg1 = event_time_ms(batched_grad, 1)
         ts = event_time_ms(batched_stored, 1)
-        out.update({"all_stages_stored_gradients_per_s": round(len(probs) / (ts / 1e3), 2),
+        out.update({"one_gradient_gradients_per_s": round(len(probs) / (tg1 / 1e3), 2),
+                    "all_stages_stored_gradients_per_s": round(len(probs) / (ts / 1e3), 2),
                     "all_stages_stored_bytes": st_bytes,
                     "all_stages_stored_max_abs_gradient_diff": float((gs - gb).abs().max())})
+        del gb, gs
     B.close()
     return out
 
@@ -402,11 +453,11 @@ def cn_measure(P, nsteps=4, K=2, dt=2e-4):
 
 
 def lmvm_measure(P):
-    """The optimiser on the GPU: (a) the 1-D optimal-initial-condition recovery (Cole-Hopf target at
-    T = 4, Gaussian-perturbed first guess, E=16 N=8 nu=0.01, RK4 dt=5e-3, 30 iterations); (b) five
-    LMVM iterations on the 3-D 16^3 N=7 mesh (4,214,784 DOF, the small scalability case) with RK-3,
-    20 steps of dt=1e-4, checkpoint every 5 steps, recovering a seeded Fourier field from its
-    state at T."""
+    """The optimiser on the GPU: the 1-D optimal-initial-condition recovery (Cole-Hopf target at
+    T = 4, Gaussian-perturbed first guess, E=16 N=8 nu=0.01, RK4 dt=5e-3, 30 iterations).  The
+    objective history comes from the 30-iteration run; the initial-condition error after k
+    iterations from runs stopped at k (the driver is deterministic, so run k ends at the k-th
+    iterate of the long run)."""
     out = {}
     nu, T, dt = 0.01, 4.0, 5e-3
     c = P.Context(1, 8, [16], [4.0], nu)
@@ -423,25 +474,19 @@ def lmvm_measure(P):
     t0 = time.perf_counter()
     u, hist, st = c.lmvm_initial_condition(guess, target, dt, n, 50, scheme="rk4", opts={"max_iters": 30})
     t1 = time.perf_counter() - t0
+    e0 = float((guess - exact0).norm())
+    ic_err = {"0": 1.0}
+    for k in (1, 2, 5, 10, 20):
+        uk, _, _ = c.lmvm_initial_condition(guess, target, dt, n, 50, scheme="rk4", opts={"max_iters": k})
+        ic_err[str(k)] = round(float((uk - exact0).norm()) / e0, 4)
+    ic_err[str(st["iters"])] = round(float((u - exact0).norm()) / e0, 4)
     out["recovery_1d"] = {"iterations": st["iters"], "evaluations": st["evals"], "seconds": round(t1, 3),
-                          "objective": [hist[0], hist[5], hist[10], hist[-1]],
-                          "ic_error_l2_relative": float((u - exact0).norm() / (guess - exact0).norm())}
+                          "objective_history": [round(h, 8) for h in hist],
+                          "ic_error_l2_relative_after_k_iterations": ic_err,
+                          "note": "the misfit at T falls ~600x while the initial condition stays ~95% off: over "
+                                  "T = 4 the unit Gaussian bump steepens and is damped, so its detail is not "
+                                  "observable at T; the recovery outcome is parity-unpinned"}
     c.close()
-    cfg = wl.C3
-    ctx = P.Context(3, cfg.N, [16, 16, 16], cfg.L, cfg.nu, dtype=torch.float64)
-    xs = [ctx.node_coords(k) for k in range(3)]
-    dev = lambda a: torch.from_numpy(a).to("cuda", torch.float64)  # noqa: E731
-    truth = dev(wl.fourier_field(xs, cfg.L, wl.C3_K, 30)[None])
-    target, _ = ctx.rk_forward(truth, 1e-4, 20, scheme="rk3")
-    guess = dev(wl.fourier_field(xs, cfg.L, wl.C3_K, 31)[None])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    u, hist, st = ctx.lmvm_initial_condition(guess, target, 1e-4, 20, 5, scheme="rk3", opts={"max_iters": 5})
-    t2 = time.perf_counter() - t0
-    out["small_case_3d"] = {"dof": ctx.ndof, "iterations": st["iters"], "evaluations": st["evals"],
-                            "seconds": round(t2, 3), "seconds_per_evaluation": round(t2 / st["evals"], 4),
-                            "objective": [hist[0], hist[-1]]}
-    ctx.close()
     torch.cuda.empty_cache()
     return out
 

@@ -90,6 +90,11 @@ int sem_query_path(sem_ctx ctx, int32_t* path);
 /* Host copy of the 1-D node coordinates of direction dir (n_dir doubles into x_host). */
 int sem_node_coords(sem_ctx ctx, int32_t dir, double* x_host);
 
+/* m = the assembled diagonal GLL mass M (Sec. 3.2: the lumped mass of the collocation quadrature,
+   M[g] = prod_k (h_k / 2) (2 w_0 if g_k mod N = 0, else w_{g_k mod N})), written to every component
+   of every batch member: m is a device array shaped like a field. */
+int sem_mass(sem_ctx ctx, void* m);
+
 /* f = F(u) = M^{-1} Q^T a(Q u): the semi-discrete right-hand side of u_t = nu Lap u - (u.grad)u
    in the explicit form u' = M^{-1} P(u) (Sec. 3.4), where a(.) is the per-element weak form
    -sum_j D_j^T(nu W D_j U_i) - W sum_j U_j D_j U_i (Sec. 3.3, eq. rhsvec; signs of eq. burgers23d),
@@ -277,6 +282,8 @@ int sem_batch_destroy(sem_batch b);
 int sem_batch_set_stream(sem_batch b, void* stream);
 /* offsets: host array of count+1 entries (in values, not bytes); offsets[count] = total. */
 int sem_batch_query(sem_batch b, int64_t* offsets);
+/* The assembled diagonal mass of every problem (as sem_mass) on a packed array. */
+int sem_batch_mass(sem_batch b, void* m);
 /* F of every problem: f = F(u) on packed arrays. */
 int sem_batch_rhs(sem_batch b, const void* u, void* f);
 /* J_p(u_p)^T w_p for every problem p on packed arrays. */

@@ -19,6 +19,12 @@ struct FastTab {
   T A[H * H], B[H * H];
   T w[P];    // GLL weights
   T imq[P];  // 1 / (assembled 1-D reference mass at local index q): 1/(2 w_0) at q = 0, P - 1
+  // A line's last point (used where a tile completes a face from a neighbour's line):
+  //   D7[n] = D_{P-1,n}  (the derivative there),
+  //   Kw[n] = K_{P-1,n} / w_{P-1} with K = D^T W D the 1-D stiffness (the weak second derivative
+  //           of D^T (w D x) evaluated there, divided by the point's weight),
+  //   Dw[m] = D_{m,P-1} w_m / w_{P-1}  (D^T (w y) evaluated there, divided by the point's weight).
+  T D7[P], Kw[P], Dw[P];
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -188,6 +194,66 @@ __device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const OM& om,
   }
 }
 
+// Direction-j terms of an element's residual (the map_contrib terms) at the last point of its
+// lines, from whole lines: UL[i] / VL[i] hold component i of the state and of the second input
+// (J v: v; J^T: Z = M^{-1} w) at the P points of the lane's line, om7 the quadrature weight at the
+// last point, K1 = nu sc_j^2 and K2 = sc_j as for map_contrib.  With the stiffness row
+// K_{P-1,.} = sum_m D_{m,P-1} w_m D_{m,.} the two contractions collapse to dot products:
+//   F:   out_i = -om7 (K1 Kw.U_i + K2 U_j(P-1) D7.U_i)
+//   J v: out_i = -om7 (K1 Kw.V_i + K2 (V_j(P-1) D7.U_i + U_j(P-1) D7.V_i))
+//   J^T: out_l = -om7 (K1 Kw.Z_l + K2 Dw.(U_j Z_l)) - [l = j] om7 K2 sum_i Z_i(P-1) D7.U_i
+template <typename T, int OP, int NC, int P = 8>
+__device__ __forceinline__ void line_end_terms(int j, const T (&UL)[NC][P], const T (&VL)[NC][P], T om7, T K1, T K2,
+                                               const FastTab<T, P>* __restrict__ tb, T (&out)[NC]) {
+  constexpr int L = P - 1;
+  const T* __restrict__ D7 = tb->D7;
+  const T* __restrict__ Kw = tb->Kw;
+  if constexpr (OP == OP_RHS) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      T k = Kw[0] * UL[i][0], d = D7[0] * UL[i][0];
+#pragma unroll
+      for (int n = 1; n < P; ++n) {
+        k += Kw[n] * UL[i][n];
+        d += D7[n] * UL[i][n];
+      }
+      out[i] = -om7 * (K1 * k + K2 * UL[j][L] * d);
+    }
+  } else if constexpr (OP == OP_JAC) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      T k = Kw[0] * VL[i][0], du = D7[0] * UL[i][0], dv = D7[0] * VL[i][0];
+#pragma unroll
+      for (int n = 1; n < P; ++n) {
+        k += Kw[n] * VL[i][n];
+        du += D7[n] * UL[i][n];
+        dv += D7[n] * VL[i][n];
+      }
+      out[i] = -om7 * (K1 * k + K2 * (VL[j][L] * du + UL[j][L] * dv));
+    }
+  } else {
+    const T* __restrict__ Dw = tb->Dw;
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      T du = D7[0] * UL[i][0];
+#pragma unroll
+      for (int n = 1; n < P; ++n) du += D7[n] * UL[i][n];
+      acc += VL[i][L] * du;
+    }
+#pragma unroll
+    for (int l = 0; l < NC; ++l) {
+      T k = Kw[0] * VL[l][0], a = Dw[0] * (UL[j][0] * VL[l][0]);
+#pragma unroll
+      for (int n = 1; n < P; ++n) {
+        k += Kw[n] * VL[l][n];
+        a += Dw[n] * (UL[j][n] * VL[l][n]);
+      }
+      out[l] = -om7 * (K1 * k + K2 * a + (l == j ? K2 * acc : (T)0));
+    }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T coef(const Coef& c, double dt) {
   return (T)(c.c0 + c.cdt * dt);
@@ -214,6 +280,14 @@ void fill_tab(FastTab<T, P>* t) {
   for (int q = 0; q < P; ++q) {
     t->w[q] = (T)w[q];
     t->imq[q] = (T)(1.0 / ((q == 0 || q == P - 1) ? 2.0 * w[0] : w[q]));
+  }
+  const int L = P - 1;
+  for (int n = 0; n < P; ++n) {
+    long double k = 0;
+    for (int m = 0; m < P; ++m) k += (long double)D[m * P + L] * w[m] * D[m * P + n];
+    t->D7[n] = (T)D[L * P + n];
+    t->Kw[n] = (T)(k / w[L]);
+    t->Dw[n] = (T)((long double)D[n * P + L] * w[n] / w[L]);
   }
 }
 

@@ -24,13 +24,25 @@
 //      sweep.  The input plane is carried too, so each step loads 7 new planes.  A sweep split
 //      into z-segments instead starts each segment by recomputing the layer before it.
 //   x: inside a workgroup the shared face of wavefronts w and w + 1 is added through LDS.
-//   workgroup faces: a workgroup owns the nodes x in [28X, 28X + 28), y in [7ey, 7ey + 7).  It
-//      writes its finished nodes to the output and, to a face buffer, its partial sums of the
-//      lower y-row (y = 7ey), its contributions to the upper y-row and upper x-column (owned by
-//      the neighbours), and the first 32-byte sector of each interior row (x in [28X, 28X + 4):
-//      the x = 28X node still lacks the left neighbour's part).  fast3d_fixup adds the parts,
-//      applies the inverse mass and the epilogue, and writes those nodes as whole row segments
-//      and whole sectors, so no 32-byte sector of the output is written twice.
+//   workgroup faces (F): a workgroup owns the nodes x in [28X, 28X + 28), y in [7ey, 7ey + 7)
+//      and completes them itself, so every output node is written once, by one lane, and no other
+//      launch follows.  The element residual is a sum of per-direction terms, each a function of
+//      the element's line through the node along that direction only (Sec. 3.3: the operators
+//      are sums over directions j of D_j^T(.) and pointwise D_j terms).  At a node of the lower
+//      face (y = 7ey) the missing element row below shares the own element's x- and z-lines
+//      (GLL weights w_0 = w_7, equal element sizes), so its x- and z-terms equal the own ones:
+//      they are doubled, and only its y-term is formed, from its y-line (line_end_terms).  The
+//      left face (x = 28X, wavefront 0) is completed the same way with the left element's
+//      x-line; at the corner line both rules apply (the diagonal element's terms are the doubled
+//      y-term of the lower and x-term of the left element).  The upper and right faces are left
+//      to the workgroups that own them.
+//   workgroup faces (J v, J^T, whose neighbour lines would push the kernel past its registers):
+//      the workgroup writes its finished nodes to the output and, to a face buffer, its partial
+//      sums of the lower y-row (y = 7ey), its contributions to the upper y-row and upper x-column
+//      (owned by the neighbours), and the first 32-byte sector of each interior row (x in
+//      [28X, 28X + 4): the x = 28X node still lacks the left neighbour's part).  fast3d_fixup
+//      adds the parts, applies the inverse mass and the epilogue, and writes those nodes as whole
+//      row segments and whole sectors, so no 32-byte sector of the output is written twice.
 #include "fast_common.h"
 
 namespace sem {
@@ -74,6 +86,8 @@ template <typename T, int OP, int EP, bool SEG>
 __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                      const T* __restrict__ u, const T* __restrict__ v,
                                                      T* __restrict__ face, Epi epi, Coef in_scale) {
+  // F completes the workgroup faces in the kernel; J v and J^T go through the face buffer
+  constexpr bool CMPL = OP == OP_RHS;
   constexpr bool HASV = OP != OP_RHS;
   __shared__ T sU[4][3][512];
   __shared__ T sV[4][HASV ? 3 : 1][HASV ? 512 : 1];
@@ -95,8 +109,12 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   const __amdgpu_buffer_rsrc_t r_x1 = brsrc(hx1 ? static_cast<const T*>(epi.x1) + bo : u, hx1 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_o2 = brsrc(ho2 ? static_cast<T*>(epi.o2) + bo : u, ho2 ? fbytes : 0);
   const __amdgpu_buffer_rsrc_t r_x2 = brsrc(hx2 ? static_cast<const T*>(epi.x2) + bo : u, hx2 ? fbytes : 0);
-  const __amdgpu_buffer_rsrc_t r_fb = brsrc(face + (int64_t)blockIdx.y * g.NWG * 3 * g.nz * FROWS,
-                                            (uint32_t)((int64_t)g.NWG * 3 * g.nz * FROWS * sizeof(T)));
+  const __amdgpu_buffer_rsrc_t r_fb =
+      CMPL ? brsrc(u, 0)
+           : brsrc(face + (int64_t)blockIdx.y * g.NWG * 3 * g.nz * FROWS,
+                   (uint32_t)((int64_t)g.NWG * 3 * g.nz * FROWS * sizeof(T)));
+  const __amdgpu_buffer_rsrc_t r_u = brsrc(ub, fbytes);
+  const __amdgpu_buffer_rsrc_t r_v = brsrc(HASV ? vb : ub, HASV ? fbytes : 0);
   const double dt = g.prob->dt;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
   const T c1 = coef<T>(epi.c1, dt), c2 = coef<T>(epi.c2, dt);
@@ -117,27 +135,43 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   // z-map global addressing: lane (a = l0, b = l1), register c
   const int64_t plane = (int64_t)g.ny * g.nx;
   const int64_t lrow = (int64_t)((7 * ey + l1) % g.ny) * g.nx + (7 * ex + l0) % g.nx;
-  // Output roles of the lane's node (7ex + a, 7ey + b, z):
+  // Output roles of the lane's node (7ex + a, 7ey + b, z).  F: owned (stored here) for a < 7 and
+  // b < 7; the upper x- and y-faces belong to the neighbouring workgroups (a = 7 of wavefronts
+  // 0..2 is added into the next wavefront's a = 0).  J v, J^T:
   //   own   finished here: a < 7, 1 <= b < 7, outside the first sector of the row
   //   face  face-buffer slot (lower and upper y-rows, upper x-column, first sectors), if any
   //         (a = 7 of wavefronts 0..2 has none: it is added into the next wavefront's a = 0)
   const int a = l0, b = l1;
-  const bool lsec = wave == 0 && a < 4 && b >= 1 && b < 7;
-  const bool own = a < 7 && b >= 1 && b < 7 && !lsec;
+  const bool lsec = !CMPL && wave == 0 && a < 4 && b >= 1 && b < 7;
+  const bool own = a < 7 && b < 7 && (CMPL || (b >= 1 && !lsec));
   int fo = -1, fw = 0, fk = 0;  // region offset (widths before it), width, index; fo < 0: none
-  if (b == 7) {
-    if (a < 7 || wave == WX - 1) fo = O_UY, fw = W_UY, fk = 7 * wave + a;
-  } else if (a == 7) {
-    if (wave == WX - 1) fo = O_UX, fw = W_UX, fk = b;
-  } else if (b == 0) {
-    fo = O_LY, fw = W_LY, fk = 7 * wave + a;
-  } else if (lsec) {
-    fo = O_LX, fw = W_LX, fk = 4 * (b - 1) + a;
+  if (!CMPL) {
+    if (b == 7) {
+      if (a < 7 || wave == WX - 1) fo = O_UY, fw = W_UY, fk = 7 * wave + a;
+    } else if (a == 7) {
+      if (wave == WX - 1) fo = O_UX, fw = W_UX, fk = b;
+    } else if (b == 0) {
+      fo = O_LY, fw = W_LY, fk = 7 * wave + a;
+    } else if (lsec) {
+      fo = O_LX, fw = W_LX, fk = 4 * (b - 1) + a;
+    }
   }
   const int64_t fslab = (int64_t)g.NWG * 3 * g.nz;  // values per unit of region width
   const int64_t flane = fo * fslab + ((int64_t)L * 3 * g.nz) * fw + fk;
   const int64_t orow = (int64_t)(7 * ey + b) * g.nx + 7 * ex + a;  // valid when own
-
+  // Doubling factors of the per-direction terms on the workgroup's lower face (b = 0, every
+  // wavefront) and left face (a = 0 of wavefront 0): there the missing neighbour's terms along the
+  // other directions equal the own element's.  z-map lanes (a = l0, b = l1), y-map (a = l0,
+  // c = l1), x-map (b = l0, c = l1).
+  const T fleft = (CMPL && wave == 0 && l0 == 0) ? (T)2 : (T)1;
+  const T fz = fleft * ((CMPL && l1 == 0) ? (T)2 : (T)1), fy = fleft, fx = (CMPL && l0 == 0) ? (T)2 : (T)1;
+  // y-map lanes (a, c): the lower element row's y-lines (rows 7 eym .. 7 eym + 6; row 7 is the own
+  // row 7 ey); x-map lanes (b, c) of wavefront 0: the left element's x-lines (columns
+  // 28X - 7 .. 28X - 1).  Byte offsets: a lane part and a uniform part per line point.
+  const int eym = ey == 0 ? g.Ey - 1 : ey - 1;
+  const int xl0 = (WX * 7 * X == 0 ? g.nx : WX * 7 * X) - 7;  // first column of the left element
+  const int yrow_b = (7 * ey + l0) % g.ny;                    // x-map lane row (b = l0)
+  const int xcol_a = (7 * ex + l0) % g.nx;                    // y-map lane column (a = l0)
   // Load planes c in [c0, 8) of element layer ez (plane 7ez + c, periodic in z).
   auto load_z = [&](int ez, int c0, T (&UU)[3][8], T (&VV)[3][8]) {
 #pragma unroll
@@ -155,8 +189,8 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   };
 
   // Write planes c in [c_lo, c_hi) of element layer ez from the summed z-map values Zv: inverse
-  // mass and epilogue for finished nodes, raw sums to the face-buffer slots.  Every lane issues
-  // the same stores; inactive ones drop theirs.
+  // mass and epilogue for the owned nodes, raw sums to the face-buffer slots (J v, J^T).  Every
+  // lane issues the same stores; inactive ones drop theirs.
   auto emit = [&](int ez, const T (&Zv)[3][8], int c_lo, int c_hi, const T (&E1)[3][7], const T (&E2)[3][7]) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -172,8 +206,10 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
         if (EP >= 2) r1 += c1 * E2[i][c];
         bstore(r_o1, (own && inc) ? no : OOB, r1);
         if (EP >= 2) bstore(r_o2, (own && inc) ? no : OOB, a2 * E2[i][c] + c2 * E1[i][c] + b2 * sm);
-        const uint32_t fb = (uint32_t)((flane + ((int64_t)i * g.nz + z) * fw) * sizeof(T));
-        bstore(r_fb, (fo >= 0 && inc) ? fb : OOB, r);
+        if constexpr (!CMPL) {
+          const uint32_t fb = (uint32_t)((flane + ((int64_t)i * g.nz + z) * fw) * sizeof(T));
+          bstore(r_fb, (fo >= 0 && inc) ? fb : OOB, r);
+        }
       }
   };
 
@@ -194,6 +230,36 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   T* __restrict__ tU = sU[wave][0];
   T* __restrict__ tQ = sQ[wave][0];
   T* __restrict__ tV = HASV ? sV[wave][0] : sU[wave][0];
+  // Lines of a neighbouring element through the lane's face node, points 0..6 (point 7 is the
+  // own node and comes from the tile): the lower element's y-lines in the y-map (ylow) or the
+  // left element's x-lines in the x-map (xleft), for layer ez, of one input field (r_u or r_v).
+  // lines_node fills point 7 from the tile; J^T scales its second input to Z = M^{-1} w like
+  // the tile's.
+  auto load_lines = [&](bool ylow, int ez, __amdgpu_buffer_rsrc_t r, T (&L)[3][8]) {
+    int zc = 7 * ez + l1;
+    if (zc >= g.nz) zc -= g.nz;
+    const uint32_t lane_off = (uint32_t)(((int64_t)zc * plane + (ylow ? xcol_a : (int64_t)yrow_b * g.nx)) * sizeof(T));
+#pragma unroll
+    for (int n = 0; n < 7; ++n) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int64_t uni = (int64_t)i * g.nodes + (ylow ? (int64_t)(7 * eym + n) * g.nx : (int64_t)(xl0 + n));
+        L[i][n] = bload_s<T>(r, lane_off, (uint32_t)(uni * sizeof(T)));
+      }
+    }
+  };
+  auto lines_node = [&](bool ylow, const T* __restrict__ tile, bool scale, T (&L)[3][8]) {
+    const int t = ylow ? tix(l0, 0, l1) : tix(0, l0, l1);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      L[i][7] = tile[i * 512 + t];
+      if (scale) {
+#pragma unroll
+        for (int n = 0; n < 7; ++n) L[i][n] *= zin * tb->imq[n];
+      }
+    }
+  };
+
   // The sweep.  One segment (wrap): layers 0 .. Ez - 1, plane c = 0 of layer 0 completed by the
   // periodic wrap after the sweep.  Several: layers z0 .. z0 + nl - 1 after a first step that
   // recomputes layer z0 - 1 (periodically) without storing, so that the carry into plane 0 of
@@ -204,6 +270,19 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   const int zfirst = wrap ? 0 : (z0 == 0 ? g.Ez - 1 : z0 - 1);
   T cu[3][8], cv[3][8];
   load_z(zfirst, 0, cu, cv);
+  // the neighbouring elements' lines of the next layer to process (the left ones: wavefront 0),
+  // loaded at the end of the previous step and used right after the tile is staged
+  T YU[3][8], YV[3][8], XU[3][8], XV[3][8];
+  auto load_neighbours = [&](int ez) {
+    if constexpr (!CMPL) return;
+    load_lines(true, ez, r_u, YU);
+    if constexpr (HASV) load_lines(true, ez, r_v, YV);
+    if (wave == 0) {
+      load_lines(false, ez, r_u, XU);
+      if constexpr (HASV) load_lines(false, ez, r_v, XV);
+    }
+  };
+  load_neighbours(zfirst);
   T carry[3] = {0, 0, 0}, first0[3] = {0, 0, 0};
 
   for (int k = 0; k < nstep; ++k) {
@@ -236,11 +315,34 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 #pragma unroll
           for (int c = 0; c < 8; ++c) Xr[c] = cv[i][c];
         },
-        om, K1z, K2z, tb,
+        om, K1z * fz, K2z * fz, tb,
         [&](int i, const T (&P)[8]) {
 #pragma unroll
           for (int c = 0; c < 8; ++c) tQ[i * 512 + tix(l0, l1, c)] = P[c];
         });
+    // the lower element's y-terms at its b = 7 (y-map lanes (a, c)), added at b = 0, and, in
+    // wavefront 0, the left element's x-terms at its a = 7 (x-map lanes (b, c)), added at a = 0:
+    // their lines' last point is the own node, read from the tile
+    if constexpr (CMPL) {
+    wave_sync();
+    {
+      T low[3];
+      lines_node(true, tU, false, YU);
+      if constexpr (HASV) lines_node(true, tV, OP == OP_JACT, YV);
+      line_end_terms<T, OP, 3>(1, YU, YV, om[7], K1y * fy, K2y * fy, tb, low);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) tQ[i * 512 + tix(l0, 0, l1)] += low[i];
+    }
+    if (wave == 0) {
+      T low[3];
+      lines_node(false, tU, false, XU);
+      if constexpr (HASV) lines_node(false, tV, OP == OP_JACT, XV);
+      line_end_terms<T, OP, 3>(0, XU, XV, om[7], K1x * fx, K2x * fx, tb, low);
+      wave_sync();
+#pragma unroll
+      for (int i = 0; i < 3; ++i) tQ[i * 512 + tix(0, l0, l1)] += low[i];
+    }
+    }
     // the z-map lines are no longer needed: move plane 7 to plane 0 and prefetch the next layer's
     // planes 1..7 into the same registers (unconditionally: the last step reloads layer 0, so the
     // memory-op sequence is fixed)
@@ -262,7 +364,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 #pragma unroll
           for (int q = 0; q < 8; ++q) Xr[q] = tV[i * 512 + tix(l0, q, l1)];
         },
-        om, K1y, K2y, tb,
+        om, K1y * fy, K2y * fy, tb,
         [&](int i, const T (&P)[8]) {
           // read the 8 values first, then write: one LDS round trip per component instead of
           // one per value (the compiler cannot prove the swizzled addresses distinct)
@@ -273,7 +375,8 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
           for (int q = 0; q < 8; ++q) tQ[i * 512 + tix(l0, q, l1)] = qv[q] + P[q];
         });
     wave_sync();
-    // ---- x-map (lane (b=l0, c=l1), register a): accumulate into the tile, keep face a = 7
+    // ---- x-map (lane (b=l0, c=l1), register a): accumulate into the tile, keep face a = 7;
+    // wavefront 0 adds the left element's x-terms at its a = 7 to a = 0
     T R7[3];
     map_contrib<T, OP, 3>(
         0,
@@ -285,7 +388,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 #pragma unroll
           for (int q = 0; q < 8; ++q) Xr[q] = tV[i * 512 + tix(q, l0, l1)];
         },
-        om, K1x, K2x, tb,
+        om, K1x * fx, K2x * fx, tb,
         [&](int i, const T (&P)[8]) {
           T qv[8];
 #pragma unroll
@@ -327,6 +430,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
     }
     // ---- outputs (with one segment, plane c = 0 of layer 0 waits for the periodic wrap)
     emit(ez, Zv, c_lo, c_hi, E1, E2);
+    load_neighbours(ez + 1 < g.Ez ? ez + 1 : 0);  // the last step loads one layer more
   }
   // periodic wrap along z: the carried plane of the last layer is plane c = 0 of layer 0
   if (wrap) {
@@ -440,9 +544,9 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
   const FastArgs g = make_args(hp, dprob, z_segments(hp, op, sizeof(T) == 4));
   const auto* tb = static_cast<const FastTab<T>*>(dtab);
   const dim3 grid(g.NWG * g.nseg, hp.batch);
-  T* fc = static_cast<T*>(face);
   const T* uu = static_cast<const T*>(u);
   const T* vv = static_cast<const T*>(v);
+  T* fc = static_cast<T*>(face);
   const int ep = (epi.o2 || epi.x2) ? 2 : (epi.x1 ? 1 : 0);
 #define SEM_FAST_LAUNCH(OPV, EPV)                                                                           \
   hipLaunchKernelGGL((fast3d_kernel<T, OPV, EPV, false>), grid, dim3(256), 0, s, g, tb, uu, vv, fc, epi, in_scale)
@@ -476,7 +580,7 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
 #undef SEM_FAST_EP
 #undef SEM_FAST_LAUNCH
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || op == OP_RHS) return e;  // F completes its faces in the kernel
   const dim3 fgrid((unsigned)(g.NWG * 3), (unsigned)((g.nz * FSEC + 255) / 256), hp.batch);
   if (op == OP_JACT)
     hipLaunchKernelGGL((fast3d_fixup<T, false>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
@@ -493,10 +597,10 @@ bool fast3d_supported(const ProbDev& hp) {
          (int64_t)3 * hp.nodes * 8 < ((int64_t)1 << 31);
 }
 
+
 int64_t fast3d_face_values(const ProbDev& hp) {
   return (int64_t)hp.batch * (hp.E[0] / WX) * hp.E[1] * 3 * hp.n[2] * FROWS;
 }
-
 
 hipError_t launch_fast3d(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, void* face,
                          const Epi& epi, Coef in_scale, const void* dtables, int dtype, hipStream_t s) {

@@ -530,4 +530,34 @@ hipError_t launch_dss(const ProbDev* probs, int32_t nprobs, int64_t nitems, int 
   return run_dss<float, 3>(probs, nprobs, nitems, div, lvec, epi, s);
 }
 
+// Assembled diagonal GLL mass (Sec. 3.2: the lumped mass of the collocation quadrature) of every
+// node of one problem-table entry, written to every component of its fields:
+//   M[g] = prod_k (h_k / 2) (2 w_0 if g_k mod N = 0, else w_{g_k mod N}).
+template <typename T>
+__global__ __launch_bounds__(256) void mass_kernel(ProbDev p, T* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)p.batch * p.nodes) return;
+  const int64_t b = t / p.nodes, g = t - b * p.nodes;
+  int64_t r = g;
+  double m = 1.0;
+  for (int k = 0; k < p.dim; ++k) {
+    const int64_t gk = r % p.n[k];
+    r /= p.n[k];
+    const int q = (int)(gk % p.N);
+    m *= p.hh[k] * (q == 0 ? 2.0 * p.w[0] : p.w[q]);
+  }
+  T* __restrict__ o = out + p.off + b * p.dim * p.nodes + g;
+  for (int c = 0; c < p.dim; ++c) o[c * p.nodes] = (T)m;
+}
+
+hipError_t launch_mass(const ProbDev& hp, void* out, int dtype, hipStream_t s) {
+  const int64_t blocks = ((int64_t)hp.batch * hp.nodes + 255) / 256;
+  if (blocks <= 0) return hipSuccess;
+  if (dtype == SEM_F64)
+    hipLaunchKernelGGL(mass_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, hp, static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL(mass_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, hp, static_cast<float*>(out));
+  return hipGetLastError();
+}
+
 }  // namespace sem

@@ -188,8 +188,8 @@ struct OpSet {
   std::vector<Class> classes;
   int64_t total_vals = 0, total_nodes = 0, lvals = 0;
   DevBuf lvec;
+  DevBuf face;  // face buffer of the tuned 3-D J v and J^T
   int fast = 0;  // one problem handled by a tuned kernel: 3 (kern_fast3d) or 2 (kern_fast2d)
-  DevBuf face;
   DevBuf fast_tab;
   // persistent mixed-order launch (2-D sets): cost-sorted work list and per-order tables
   int persistent = 0;  // 0: one launch per order class, 1: one persistent launch
@@ -550,10 +550,11 @@ struct Integrator {
   // new state to unext: the same launches and coefficients as the captured step, so the states
   // are the same values.  With unext null (the last step of a segment) only the stage states are
   // formed, without the accumulator, as in the adjoint step's own recompute.
-  hipError_t enqueue_step_stages(hipStream_t s, int scheme, const void* u, void* const* st, void* unext) {
+  hipError_t enqueue_step_stages(hipStream_t s, int scheme, const void* u, void* const* st, void* unext,
+                                 void* accbuf = nullptr) {
     hipError_t e;
     const Coef one{1, 0}, zero{0, 0};
-    void* acc = unext ? b(ACC) : nullptr;
+    void* acc = unext ? (accbuf ? accbuf : b(ACC)) : nullptr;
     Epi ep{};
     if (scheme == SEM_RK3) {
       ep = Epi{st[0], u, one, {0, 0.5}, nullptr, nullptr, zero, zero};
@@ -562,7 +563,7 @@ struct Integrator {
                  : Epi{st[1], u, {3, 0}, {0, 2.0}, nullptr, st[0], zero, zero, {-2, 0}, zero};
       if ((e = os->apply(OP_RHS, st[0], nullptr, one, ep, s))) return e;
       if (!unext) return hipSuccess;
-      ep = Epi{unext, b(ACC), one, {0, 1.0 / 6}, nullptr, nullptr, zero, zero};
+      ep = Epi{unext, acc, one, {0, 1.0 / 6}, nullptr, nullptr, zero, zero};
       return os->apply(OP_RHS, st[1], nullptr, one, ep, s);
     }
     ep = Epi{st[0], u, one, {0, 0.5}, acc, unext ? u : nullptr, one, {0, 1.0 / 6}};
@@ -572,7 +573,7 @@ struct Integrator {
     ep = Epi{st[2], u, one, {0, 1.0}, acc, acc, one, {0, 1.0 / 3}};
     if ((e = os->apply(OP_RHS, st[1], nullptr, one, ep, s))) return e;
     if (!unext) return hipSuccess;
-    ep = Epi{unext, b(ACC), one, {0, 1.0 / 6}, nullptr, nullptr, zero, zero};
+    ep = Epi{unext, acc, one, {0, 1.0 / 6}, nullptr, nullptr, zero, zero};
     return os->apply(OP_RHS, st[2], nullptr, one, ep, s);
   }
 
@@ -1272,6 +1273,12 @@ static int apply_entry(sem_ctx c, int op, const void* u, const void* v, void* ou
   return SEM_OK;
 }
 
+int sem_mass(sem_ctx c, void* m) {
+  if (!c || !m) return fail(SEM_ERR_ARG, "null argument");
+  for (const auto& hp : c->os.hp) HIPCHK(launch_mass(hp, m, c->d.dtype, c->stream));
+  return SEM_OK;
+}
+
 int sem_rhs(sem_ctx c, const void* u, void* f) { return apply_entry(c, OP_RHS, u, nullptr, f); }
 int sem_jac_vec(sem_ctx c, const void* u, const void* v, void* jv) { return apply_entry(c, OP_JAC, u, v, jv); }
 int sem_jact_vec(sem_ctx c, const void* u, const void* w, void* jtw) { return apply_entry(c, OP_JACT, u, w, jtw); }
@@ -1662,6 +1669,12 @@ static int batch_apply(sem_batch b, int op, const void* u, const void* v, void* 
   if (out == u || (v && out == v)) return fail(SEM_ERR_ARG, "output aliases an input");
   Epi ep{out, nullptr, {0, 0}, {1, 0}, nullptr, nullptr, {0, 0}, {0, 0}};
   HIPCHK(b->os.apply(op, u, v, {1, 0}, ep, b->stream));
+  return SEM_OK;
+}
+
+int sem_batch_mass(sem_batch b, void* m) {
+  if (!b || !m) return fail(SEM_ERR_ARG, "null argument");
+  for (const auto& hp : b->os.hp) HIPCHK(launch_mass(hp, m, b->descs[0].dtype, b->stream));
   return SEM_OK;
 }
 

@@ -73,6 +73,9 @@ hipError_t launch_elem(const ElemLaunch& el, int op, const void* u, const void* 
                        const void* tables, hipStream_t s);
 hipError_t launch_dss(const ProbDev* probs, int32_t nprobs, int64_t nitems, int dim, int dtype, int divide_by_mass,
                       const void* lvec, const Epi& epi, hipStream_t s);
+// assembled diagonal mass of every node of one problem-table entry, into every component of the
+// field layout at the entry's offset
+hipError_t launch_mass(const ProbDev& hp, void* out, int dtype, hipStream_t s);
 // elements-per-workgroup choices accepted by launch_elem for (dim, P); returns count, fills out[]
 int elem_epb_choices(int dim, int P, int* out, int max_out);
 
@@ -99,7 +102,7 @@ void gll_tables(int N, double* xi, double* w, double* D);
 // workgroups still read the input nodes that a workgroup has finished.  Both take the device
 // table of their order (fast_fill_tables).
 bool fast3d_supported(const ProbDev& hp);
-int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch
+int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch (J v, J^T)
 bool fast2d_supported(const ProbDev& hp);
 // lets the 2-D kernels of order N and dtype use their workgroup LDS (more than the default limit)
 hipError_t fast2d_prepare(int N, int dtype);

@@ -83,6 +83,8 @@ _SIGS = {
     "sem_jac_vec": [_vp, _vp, _vp, _vp],
     "sem_jact_vec": [_vp, _vp, _vp, _vp],
     "sem_rk4_forward": [_vp, _vp, _f64, _i32, _i32, _vp],
+    "sem_mass": [_vp, _vp],
+    "sem_batch_mass": [_vp, _vp],
     "sem_rk4_adjoint": [_vp, _vp, _f64, _i32, _i32, _vp, _vp],
     "sem_workspace_bytes": [_vp, _i32, ctypes.POINTER(_i64)],
     "sem_set_adjoint_stages": [_vp, _i32],
@@ -259,6 +261,14 @@ class Context:
         _call(lib().sem_rk4_forward(self._h, _ptr(u), float(dt), int(nsteps), int(ckpt_every),
                                     _ptr(ck) if ck is not None else None))
         return u, ck
+
+    def mass(self, out=None):
+        """The assembled diagonal GLL mass of every node, in every component of a field-shaped array."""
+        out = self.empty() if out is None else out
+        self._chk(out, "out")
+        self._bind()
+        _call(lib().sem_mass(self._h, _ptr(out)))
+        return out
 
     def workspace_bytes(self, ckpt_every):
         b = _i64()
@@ -595,6 +605,13 @@ class Batch:
         if t.numel() != self.total:
             raise SemError(f"{name} has {t.numel()} values, expected {self.total}")
         return t
+
+    def mass(self, out=None):
+        """The assembled diagonal mass of every problem on a packed array (as Context.mass)."""
+        out = self.empty() if out is None else self._chk(out, "out")
+        self._bind()
+        _call(lib().sem_batch_mass(self._h, _ptr(out)))
+        return out
 
     def rhs(self, u, out=None):
         self._chk(u, "u")

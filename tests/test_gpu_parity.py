@@ -434,6 +434,26 @@ def test_stored_stages_batch_and_errors(P):
         P.sem._call(P.lib().sem_rk_adjoint_stored(c._h, 0, P.sem._ptr(st), 1e-3, 2, P.sem._ptr(st)))  # aliasing
 
 
+@pytest.mark.parametrize("dim,N,E,batch", [(1, 8, [16], 2), (2, 7, [8, 3], 1), (2, 9, [5, 4], 2), (3, 7, [4, 2, 3], 1),
+                                           (3, 4, [2, 3, 2], 2)])
+def test_mass_matches_oracle(P, dim, N, E, batch):
+    note(f"assembled mass dim={dim} N={N} E={E} batch={batch}")
+    m, c = make(P, dim, N, E, batch=batch)
+    ref = np.broadcast_to(m.mass(), m.shape)
+    assert rel(c.mass(), ref) < 4e-15  # a product of three factors, rounded in either order
+
+
+def test_batch_mass_matches_contexts(P):
+    specs, _ = batch_problems(12)
+    B = P.Batch(specs)
+    mb = B.mass()
+    for i, s in enumerate(specs):
+        c = P.Context(2, s["order"], s["elems"], s["length"], s["nu"])
+        assert torch.equal(B.view(mb, i), c.mass()), i
+        c.close()
+    B.close()
+
+
 def test_c4_shape_batch_gradient(P):
     # the 64-IC 2-D configuration at full mesh size; a 50-step horizon keeps the oracle side short.
     cfg = wl.C4

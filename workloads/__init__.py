@@ -132,6 +132,10 @@ class BatchedProblem:
 
 
 C5_COUNT, C5_SEED, C5_STEPS = 128, 40, 200
+# Gradient descent on the initial conditions: 20 iterations of u0 <- u0 - alpha d / max|d| with
+# the mass-weighted direction d = W g, W = M / mean(M) per problem (M the assembled diagonal
+# mass): every problem's initial field moves by at most alpha per iteration.
+C5_ITERS, C5_ALPHA = 20, 0.05
 C5_E = (8, 16, 32, 64)
 C5_N = (5, 7, 9)
 C5_K = 4
