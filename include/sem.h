@@ -117,6 +117,18 @@ int sem_jact_vec(sem_ctx ctx, const void* u, const void* w, void* jtw);
    The four stage updates are fused into the summation kernels; one step is a captured graph. */
 int sem_rk4_forward(sem_ctx ctx, void* u, double dt, int32_t nsteps, int32_t ckpt_every, void* ckpt);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): sem_rk4_forward with the same arguments, results and
+   checkpoints, that allocates nothing.  Its three stage states and its stage accumulator live in a
+   64 MiB file-scope device array that each GPU holds for the life of the process (its address is
+   resolved in sem_setup); a state may therefore hold at most (64 MiB / 4) rounded down to 256 bytes,
+   i.e. about 2.1 M FP64 values (batch * ndof), else SEM_ERR_ARG with a message naming the limit.
+   The steps are launched one by one (no graph is captured or instantiated) and no non-finite check
+   runs.  Every call on one GPU shares that GPU's array and leaves its contents behind: calls that
+   overlap in time on one GPU (other streams, other contexts, other threads) race on it and must be
+   ordered by the caller.  The context itself comes from sem_setup, which does allocate. */
+int sem_rk4_forward_noalloc(sem_ctx ctx, void* u, double dt, int32_t nsteps, int32_t ckpt_every, void* ckpt);
+
 /* Discrete adjoint of sem_rk4_forward (Sec. 4.1, eqs. adjointloop, initadj, gradient, adjtime,
    for the classical RK4 tableau): on entry lam holds lambda_N = dPhi/du(T); on exit lambda_0 =
    dPhi/du_0.  Uses the checkpoints written by sem_rk4_forward with the same dt, nsteps and

@@ -1154,9 +1154,43 @@ struct Lmvm {
 
 }  // namespace
 
+// Scratch of the allocation-free RK4 forward (sem_rk4_forward_noalloc): its three stage states and
+// the stage accumulator.  Each device holds its own copy of the array for the life of the process;
+// host code reaches it only through the address that hipGetSymbolAddress returns for the current
+// device (the array's name is a host-side stand-in, not a device address).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// This device's scratch address, resolved once per device with that device current.
+int scratch_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    return fail(SEM_ERR_UNSUPPORTED, "device %d beyond the %d devices the scratch table covers", dev,
+                SCRATCH_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SEM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SEM_OK;
+}
+}  // namespace
+
 struct sem_ctx_s {
   sem_desc d{};
   hipStream_t stream = nullptr;
+  void* scratch = nullptr;     // this device's allocation-free scratch (scratch_address)
   hipEvent_t chain = nullptr;  // orders work across a change of stream (chain_streams)
   OpSet os;
   Integrator integ;
@@ -1204,6 +1238,10 @@ int sem_setup(const sem_desc* desc, void* stream, sem_ctx* out) {
   c->d = *desc;
   c->stream = static_cast<hipStream_t>(stream);
   if ((rc = build_opset(c->os, desc, 1, true))) {
+    delete c;
+    return rc;
+  }
+  if ((rc = scratch_address(&c->scratch))) {
     delete c;
     return rc;
   }
@@ -1385,6 +1423,35 @@ int sem_set_adjoint_stages(sem_ctx c, int32_t mode) {
 
 int sem_rk4_forward(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt) {
   return sem_rk_forward(c, SEM_RK4, u, dt, nsteps, K, ckpt);
+}
+
+int sem_rk4_forward_noalloc(sem_ctx c, void* u, double dt, int32_t nsteps, int32_t K, void* ckpt) {
+  if (!c) return fail(SEM_ERR_ARG, "null context");
+  if (!u) return fail(SEM_ERR_ARG, "null u");
+  int rc = check_steps(dt, nsteps, K, ckpt != nullptr);
+  if (rc) return rc;
+  if (ckpt && ckpt == u) return fail(SEM_ERR_ARG, "ckpt aliases u");
+  // three stage states and the accumulator, each rounded up to the array's 256-byte alignment
+  const int64_t bytes = c->integ.n * (int64_t)c->os.ts;
+  const int64_t slot = (bytes + 255) / 256 * 256;
+  if (4 * slot > (int64_t)NOALLOC_SCRATCH_BYTES)
+    return fail(SEM_ERR_ARG,
+                "state of %lld bytes: the allocation-free RK4 forward keeps 4 states (%lld bytes) in a scratch of "
+                "%zu bytes; use sem_rk4_forward",
+                (long long)bytes, (long long)(4 * slot), NOALLOC_SCRATCH_BYTES);
+  if (!c->scratch) return fail(SEM_ERR_HIP, "scratch address not resolved");
+  char* sp = static_cast<char*>(c->scratch);
+  void* const st[3] = {sp, sp + slot, sp + 2 * slot};
+  void* const acc = sp + 3 * slot;
+  if ((rc = c->integ.set_dt(dt, false, c->stream))) return rc;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    if (ckpt && k % K == 0)
+      HIPCHK(hipMemcpyAsync(static_cast<char*>(ckpt) + (size_t)(k / K) * bytes, u, bytes, hipMemcpyDeviceToDevice,
+                            c->stream));
+    // the captured step's launches and coefficients, the new state written over u
+    HIPCHK(c->integ.enqueue_step_stages(c->stream, SEM_RK4, u, st, u, acc));
+  }
+  return SEM_OK;
 }
 
 int sem_rk_adjoint(sem_ctx c, int32_t scheme, const void* ckpt, double dt, int32_t nsteps, int32_t K, void* lam,

@@ -83,6 +83,7 @@ _SIGS = {
     "sem_jac_vec": [_vp, _vp, _vp, _vp],
     "sem_jact_vec": [_vp, _vp, _vp, _vp],
     "sem_rk4_forward": [_vp, _vp, _f64, _i32, _i32, _vp],
+    "sem_rk4_forward_noalloc": [_vp, _vp, _f64, _i32, _i32, _vp],
     "sem_mass": [_vp, _vp],
     "sem_batch_mass": [_vp, _vp],
     "sem_rk4_adjoint": [_vp, _vp, _f64, _i32, _i32, _vp, _vp],
@@ -269,6 +270,19 @@ class Context:
         self._bind()
         _call(lib().sem_mass(self._h, _ptr(out)))
         return out
+
+    def rk4_forward_noalloc(self, u, dt, nsteps, ckpt_every=0, ckpt=None):
+        """sem_rk4_forward_noalloc: RK4 in place on u (u0 in, u(T) out) with the library allocating
+        nothing; the caller passes u and, if ckpt_every, the checkpoint array
+        [nsteps/K][batch][C][...].  Returns (u, ckpt)."""
+        self._chk(u, "u")
+        if ckpt_every and (ckpt is None or not ckpt.is_contiguous() or ckpt.dtype != self.dtype or
+                           ckpt.numel() != (nsteps // ckpt_every) * self.batch * self.ndof):
+            raise SemError("ckpt must be a contiguous [nsteps/K][batch][C][...] array of the context's dtype")
+        self._bind()
+        _call(lib().sem_rk4_forward_noalloc(self._h, _ptr(u), float(dt), int(nsteps), int(ckpt_every),
+                                            _ptr(ckpt) if ckpt_every else None))
+        return u, ckpt
 
     def workspace_bytes(self, ckpt_every):
         b = _i64()
