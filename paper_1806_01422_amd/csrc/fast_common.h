@@ -27,6 +27,30 @@ struct FastTab {
   T D7[P], Kw[P], Dw[P];
 };
 
+// The same (uniform) table pointer, opaque to the compiler and in the constant address space:
+// loads through it are scalar loads that cannot be hoisted across the point where it is taken.
+// A kernel that sweeps a loop takes one per phase of the loop body, so the table's coefficients
+// are re-read from the scalar cache where a phase needs them instead of being held in scalar
+// registers for the whole loop (which overflows them: the compiler then parks the values in
+// vector-register lanes and restores each with two lane reads before every use).
+template <typename P>
+using const_ptr = const __attribute__((address_space(4))) P*;
+template <typename P>
+__device__ __forceinline__ const_ptr<P> phase_ptr(const P* p) {
+  uint64_t v = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(v));
+  return reinterpret_cast<const_ptr<P>>(v);
+}
+
+// omega at register s: a lane factor times a GLL weight (uniform, read through WP), formed where
+// it is used
+template <typename T, typename WP>
+struct OmLane {
+  T f;
+  WP w;
+  __device__ __forceinline__ T operator[](int s) const { return f * w[s]; }
+};
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -74,8 +98,8 @@ __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
 //   e_m = x_m + x_{P-1-m}, o_m = x_m - x_{P-1-m};  y_i = s_i + d_i, y_{P-1-i} = s_i - d_i  (i < H)
 //   D:   s_i = sum_m A[i][m] o_m,  d_i = sum_m B[i][m] e_m
 //   D^T: s_i = sum_m B[m][i] o_m,  d_i = sum_m A[m][i] e_m
-template <bool TR, typename T, int P>
-__device__ __forceinline__ void contract(const T (&x)[P], T (&y)[P], const FastTab<T, P>* __restrict__ tb) {
+template <bool TR, typename T, int P, typename TB>
+__device__ __forceinline__ void contract(const T (&x)[P], T (&y)[P], TB tb) {
   constexpr int H = P / 2;
   T e[H], o[H];
 #pragma unroll
@@ -83,8 +107,8 @@ __device__ __forceinline__ void contract(const T (&x)[P], T (&y)[P], const FastT
     e[m] = x[m] + x[P - 1 - m];
     o[m] = x[m] - x[P - 1 - m];
   }
-  const T* __restrict__ A = tb->A;
-  const T* __restrict__ B = tb->B;
+  const auto A = tb->A;
+  const auto B = tb->B;
 #pragma unroll
   for (int i = 0; i < H; ++i) {
     T s, d;
@@ -116,9 +140,8 @@ __device__ __forceinline__ void contract(const T (&x)[P], T (&y)[P], const FastT
 // receives the contribution to component i.  om[s] is the quadrature weight at register s (an array
 // or an indexable object),
 // K1 = nu sc_j^2, K2 = sc_j (the 2/h_j of D on the physical element folded in).
-template <typename T, int OP, int NC, int P = 8, typename LU, typename LV, typename OM, typename EM>
-__device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const OM& om, T K1, T K2,
-                                            const FastTab<T, P>* __restrict__ tb, EM emit) {
+template <typename T, int OP, int NC, int P = 8, typename LU, typename LV, typename OM, typename TB, typename EM>
+__device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const OM& om, T K1, T K2, TB tb, EM emit) {
   T c1[P], cu[P];
   {
     T Uj[P];
@@ -202,12 +225,12 @@ __device__ __forceinline__ void map_contrib(int j, LU ldU, LV ldV, const OM& om,
 //   F:   out_i = -om7 (K1 Kw.U_i + K2 U_j(P-1) D7.U_i)
 //   J v: out_i = -om7 (K1 Kw.V_i + K2 (V_j(P-1) D7.U_i + U_j(P-1) D7.V_i))
 //   J^T: out_l = -om7 (K1 Kw.Z_l + K2 Dw.(U_j Z_l)) - [l = j] om7 K2 sum_i Z_i(P-1) D7.U_i
-template <typename T, int OP, int NC, int P = 8>
+template <typename T, int OP, int NC, int P = 8, typename TB>
 __device__ __forceinline__ void line_end_terms(int j, const T (&UL)[NC][P], const T (&VL)[NC][P], T om7, T K1, T K2,
-                                               const FastTab<T, P>* __restrict__ tb, T (&out)[NC]) {
+                                               TB tb, T (&out)[NC]) {
   constexpr int L = P - 1;
-  const T* __restrict__ D7 = tb->D7;
-  const T* __restrict__ Kw = tb->Kw;
+  const auto D7 = tb->D7;
+  const auto Kw = tb->Kw;
   if constexpr (OP == OP_RHS) {
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
@@ -232,7 +255,7 @@ __device__ __forceinline__ void line_end_terms(int j, const T (&UL)[NC][P], cons
       out[i] = -om7 * (K1 * k + K2 * (VL[j][L] * du + UL[j][L] * dv));
     }
   } else {
-    const T* __restrict__ Dw = tb->Dw;
+    const auto Dw = tb->Dw;
     T acc = 0;
 #pragma unroll
     for (int i = 0; i < NC; ++i) {

@@ -31,46 +31,59 @@ namespace sem {
 namespace {
 
 using namespace fast;
-constexpr int EW = 8;    // elements per wavefront along x
-constexpr int MAXW = 8;  // wavefronts per workgroup
-
-// omega at register s: a lane factor times a GLL weight (uniform), formed where it is used
-template <typename T>
-struct OmLane {
-  T f;
-  const T* __restrict__ w;
-  __device__ __forceinline__ T operator[](int s) const { return f * w[s]; }
+// Lane layout per order.  Up to 8 points per line (orders 3, 5, 7) an element has 8 lanes and a
+// wavefront 8 elements; with 10 points (order 9) an element has 16 lanes (6 of them padding) and a
+// wavefront 4 elements.  A workgroup holds at most MAXW wavefronts: a whole element row for
+// P <= 8 (up to 64 elements); for P = 10 at most 16 elements, so longer rows are split into
+// x-segments of one workgroup each (see "x-segments" above).
+template <int P>
+struct Lay {
+  static constexpr int LPE = P <= 8 ? 8 : 16;  // lanes per element
+  static constexpr int EW = 64 / LPE;          // elements per wavefront along x
+  static constexpr int MAXW = P <= 8 ? 8 : 4;  // wavefronts per workgroup
+  // Padded LDS index of point (a, b) of element slot e: TE e + TB b + a.  Modulo 32 (the 8-byte
+  // bank pairs of 64 banks), with LPE = 8: 8e + a + 9b, so with b fixed (y-map) the 32 lanes
+  // e in 0..3 (or 4..7), a in 0..7 hit 32 distinct pairs, and with a fixed (x-map)
+  // 8 ((e + b) mod 4) + b is distinct over b in 0..7, e in 0..3.  With LPE = 16: 16e + 17b + a,
+  // so with b fixed a + 16e (a in 0..15, e in 0..1) is distinct, and with a fixed 17b + 16e is:
+  // 17b mod 32 runs through the even residues 0..14 and the odd ones 17..31 for b in 0..15.
+  // Either map addresses its registers as one lane base plus immediate offsets.
+  static constexpr int TB = LPE + 1;
+  static constexpr int TE = LPE == 8 ? 72 : 176;  // >= P TB, and 8 (or 16) modulo 32
+  static constexpr int TC = EW * TE;              // component stride
 };
+
 
 struct Fast2Args {
   int Ex, Ey, nx, ny;
-  int nw;    // wavefronts per workgroup (Ex / 8)
+  int nw;    // wavefronts per workgroup
+  int nxs;   // x-segments per element row (Ex / (nw EW))
   int S;     // element rows per segment
-  int nseg;  // segments per batch member
-  int nwg;   // workgroups (batch * nseg)
+  int nseg;  // row segments per batch member
+  int nwg;   // workgroups (batch * nseg * nxs)
   double hh[2], sc[2], nu;
   int64_t nodes;  // per component
   const ProbDev* prob;
 };
 
-// Padded LDS index of point (a, b) of element slot e: 72e + 9b + a (rows of 9, elements of 72).
-// Modulo 32 (the 8-byte bank pairs of 64 banks) this is 8e + a + 9b: with b fixed (y-map) the
-// 32 lanes e in 0..3 (or 4..7), a in 0..7 hit 32 distinct pairs, and with a fixed (x-map)
-// 8 ((e + b) mod 4) + b is distinct over b in 0..7, e in 0..3.  Either map addresses its 8
-// registers as one lane base plus immediate offsets.
-constexpr int TE = 72, TB = 9, TC = EW * TE;  // element, row and component strides
-__device__ __forceinline__ int tix2(int e, int a, int b) { return TE * e + TB * b + a; }
+template <int P>
+__device__ __forceinline__ int tix2(int e, int a, int b) {
+  return Lay<P>::TE * e + Lay<P>::TB * b + a;
+}
 
 // LDS per workgroup: per wavefront a tile of NIN * 2 components x TC points, then the x-face
 // exchange between wavefronts [step parity][wavefront][component][b].
-template <typename T>
+template <typename T, int P>
 constexpr size_t lds_bytes(int nin, int nw) {
-  return sizeof(T) * ((size_t)nw * nin * 2 * TC + (size_t)2 * nw * 2 * 8);
+  return sizeof(T) * ((size_t)nw * nin * 2 * Lay<P>::TC + (size_t)2 * nw * 2 * Lay<P>::LPE);
 }
 
-// The work of one workgroup: a row segment of one field (all values wavefront-uniform).
+// The work of one workgroup: a row segment of one field, or of one x-segment of it (all values
+// wavefront-uniform).
 struct Fast2Job {
   int Ey, nx, ny, nw, y0, nrows;
+  int x0;      // first element column of the workgroup
+  bool xsplit; // the row is split into x-segments: the left face is completed here
   int64_t nodes;  // per component
   int64_t bo;     // values before the field (batch member or packed problem)
   double hh[2], sc[2], nu, dt;
@@ -85,6 +98,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
   constexpr bool HASV = OP != OP_RHS;
   constexpr int NIN = HASV ? 2 : 1;
   constexpr int N = P - 1;
+  constexpr int LPE = Lay<P>::LPE, EW = Lay<P>::EW, TC = Lay<P>::TC;
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = g.nw;
@@ -103,12 +117,23 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
   const T c1 = coef<T>(epi.c1, dt), c2 = coef<T>(epi.c2, dt);
 
-  const int l0 = lane & 7, e = lane >> 3;  // y-map: a = l0; x-map: b = l0
-  const int a = l0;
-  const int lp = l0 < P ? l0 : N;  // table index of the lane's point (padding lanes: any valid one)
+  const int e = lane / LPE;  // element slot of the wavefront
+  const int a = lane % LPE;  // y-map: column a of the lane's line (>= P: padding)
+  // x-map: row b = l0.  Padding rows of the 8-lane layout stay inside the 72-value element block;
+  // with 16 lanes they would not, so those padding lanes take row N (and write the same values
+  // as its own lane).
+  const int l0 = P > 8 ? min(a, N) : a;
+  const int lp = min(a, N);  // table index of the lane's point (padding lanes: point N)
   // quadrature weight omega = (h_x h_y / 4) w_a w_b; with the lane holding one index and the
   // register the other, the same lane factor serves both maps
-  const OmLane<T> om{(T)(g.hh[0] * g.hh[1]) * tb->w[lp], tb->w};
+  const T omf = (T)(g.hh[0] * g.hh[1]) * tb->w[lp];
+  // x-segmented rows: the workgroup's left face (column N x0, point a = 0 of wavefront 0's slot
+  // 0) is completed here.  The missing left element shares the own element's y-lines there, so
+  // its y-terms equal the own ones and are doubled; its x-terms come from its x-lines
+  // (line_end_terms).  The right face is left to the next x-segment.
+  constexpr bool SPLITS = P > 8;  // only order 9 splits rows into x-segments
+  const bool lface = SPLITS && g.xsplit && wave == 0 && e == 0;
+  const T omyf = (lface && a == 0) ? (T)2 * omf : omf;
   const T K1x = (T)(g.nu * g.sc[0] * g.sc[0]), K1y = (T)(g.nu * g.sc[1] * g.sc[1]);
   const T K2x = (T)g.sc[0], K2y = (T)g.sc[1];
   // inverse assembled mass, lane factor of the y-map
@@ -117,10 +142,10 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
 
   T* __restrict__ tU = lds + (size_t)wave * NIN * 2 * TC;
   T* __restrict__ tV = tU + 2 * TC;
-  T* __restrict__ sEx = lds + (size_t)nw * NIN * 2 * TC;  // [2][nw][2][8]
+  T* __restrict__ sEx = lds + (size_t)nw * NIN * 2 * TC;  // [2][nw][2][LPE]
 
   // y-map global addressing: column of the lane's line, periodic in x and y
-  int col = N * (EW * wave + e) + (a <= N ? a : N);
+  int col = N * (g.x0 + EW * wave + e) + (a <= N ? a : N);
   if (col >= g.nx) col -= g.nx;
 
   // the lane's byte offset in a grid row; the row and component part is uniform (scalar offset)
@@ -155,19 +180,21 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
 #pragma unroll
     for (int i = 0; i < 2; ++i) vlast[i] = cv[i][N];
     if constexpr (OP == OP_JACT) {
+      const auto ts = phase_ptr(tb);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int b = 0; b < P; ++b) cv[i][b] *= zin * tb->imq[b];
+        for (int b = 0; b < P; ++b) cv[i][b] *= zin * ts->imq[b];
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int b = 0; b < P; ++b) {
-        tU[i * TC + tix2(e, a, b)] = cu[i][b];
-        if constexpr (HASV) tV[i * TC + tix2(e, a, b)] = cv[i][b];
+        tU[i * TC + tix2<P>(e, a, b)] = cu[i][b];
+        if constexpr (HASV) tV[i * TC + tix2<P>(e, a, b)] = cv[i][b];
       }
     T r[2][P];
+    const auto ty = phase_ptr(tb);
     map_contrib<T, OP, 2, P>(
         1,
         [&](int i, T (&X)[P]) {
@@ -178,7 +205,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
 #pragma unroll
           for (int b = 0; b < P; ++b) X[b] = cv[i][b];
         },
-        om, K1y, K2y, tb,
+        OmLane<T, decltype(ty->w + 0)>{omyf, ty->w}, K1y, K2y, ty,
         [&](int i, const T (&Pv)[P]) {
 #pragma unroll
           for (int b = 0; b < P; ++b) r[i][b] = Pv[b];
@@ -196,21 +223,51 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
     if constexpr (!HASV) load_rows(ey_next, 1, true, false, cu, cv);
     wave_sync();
     // ---- x-map (lane (b = l0, e), register a): x-direction part, written over component i of
-    // the state tile once that component has been read
+    // the state tile once that component has been read.  On a left face, the left element's
+    // x-terms at its last point are added at a = 0 (its lines' last point is the own node).
+    T lowX[2] = {0, 0};
+    if (SPLITS && lface) {
+      const auto tl = phase_ptr(tb);
+      T XU[2][P], XV[2][P];
+      const uint32_t rb = (uint32_t)((int64_t)((N * ey + l0) % g.ny) * g.nx * sizeof(T));
+      const int xl0 = (g.x0 == 0 ? g.nx : N * g.x0) - N;  // first column of the left element
+#pragma unroll
+      for (int p = 0; p < N; ++p)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const uint32_t uni = (uint32_t)((i * g.nodes + xl0 + p) * sizeof(T));
+          XU[i][p] = bload_s<T>(r_u, rb, uni);
+          if constexpr (HASV) XV[i][p] = bload_s<T>(r_v, rb, uni);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        XU[i][N] = tU[i * TC + tix2<P>(e, 0, l0)];
+        if constexpr (HASV) {
+          XV[i][N] = tV[i * TC + tix2<P>(e, 0, l0)];
+          if constexpr (OP == OP_JACT) {
+#pragma unroll
+            for (int p = 0; p < N; ++p) XV[i][p] *= zin * tl->imq[p];
+          }
+        }
+      }
+      line_end_terms<T, OP, 2, P>(0, XU, XV, omf * tl->w[N], K1x, K2x, tl, lowX);
+    }
+    const auto tx = phase_ptr(tb);
     map_contrib<T, OP, 2, P>(
         0,
         [&](int i, T (&X)[P]) {
 #pragma unroll
-          for (int q = 0; q < P; ++q) X[q] = tU[i * TC + tix2(e, q, l0)];
+          for (int q = 0; q < P; ++q) X[q] = tU[i * TC + tix2<P>(e, q, l0)];
         },
         [&](int i, T (&X)[P]) {
 #pragma unroll
-          for (int q = 0; q < P; ++q) X[q] = tV[i * TC + tix2(e, q, l0)];
+          for (int q = 0; q < P; ++q) X[q] = tV[i * TC + tix2<P>(e, q, l0)];
         },
-        om, K1x, K2x, tb,
+        OmLane<T, decltype(tx->w + 0)>{omf, tx->w}, K1x, K2x, tx,
         [&](int i, const T (&Pv)[P]) {
+          tU[i * TC + tix2<P>(e, 0, l0)] = SPLITS ? Pv[0] + lowX[i] : Pv[0];
 #pragma unroll
-          for (int q = 0; q < P; ++q) tU[i * TC + tix2(e, q, l0)] = Pv[q];
+          for (int q = 1; q < P; ++q) tU[i * TC + tix2<P>(e, q, l0)] = Pv[q];
         });
     if constexpr (HASV) load_rows(ey_next, 1, true, true, cu, cv);
     wave_sync();
@@ -218,25 +275,25 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int b = 0; b < P; ++b) r[i][b] += tU[i * TC + tix2(e, a, b)];
+      for (int b = 0; b < P; ++b) r[i][b] += tU[i * TC + tix2<P>(e, a, b)];
     // ---- x-direction summation: the a = N line of slot e goes to the a = 0 line of slot e + 1
     // (inside the wavefront through the tile, across wavefronts through sEx, double-buffered by
     // step parity: one barrier per step)
     const int par = k & 1;
     wave_sync();
     if (a == N) {
-      T* __restrict__ dst = (e < EW - 1) ? tU + 8 * e : sEx + ((par * nw + wave) * 2) * 8;
-      const int ist = (e < EW - 1) ? 64 : 8;
+      T* __restrict__ dst = (e < EW - 1) ? tU + LPE * e : sEx + ((par * nw + wave) * 2) * LPE;
+      const int ist = (e < EW - 1) ? 64 : LPE;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int b = 0; b < P; ++b) dst[i * ist + b] = r[i][b];
     }
     __syncthreads();
-    if (a == 0) {
+    if (a == 0 && !lface) {  // a left face has its left element's terms already
       const int wl = wave == 0 ? nw - 1 : wave - 1;
-      const T* __restrict__ src = (e > 0) ? tU + 8 * (e - 1) : sEx + ((par * nw + wl) * 2) * 8;
-      const int ist = (e > 0) ? 64 : 8;
+      const T* __restrict__ src = (e > 0) ? tU + LPE * (e - 1) : sEx + ((par * nw + wl) * 2) * LPE;
+      const int ist = (e > 0) ? 64 : LPE;
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -251,6 +308,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
     // ---- outputs: grid rows N ey .. N ey + N - 1, lanes a < N (inverse mass for F and J v); all
     // epilogue operands are read first (o2 may alias x2)
     const uint32_t vo = (st && a < N) ? lcol : OOB;
+    const auto te = phase_ptr(tb);
     T E1[2][N], E2[2][N];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -263,7 +321,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int b = 0; b < N; ++b) {
-        const T sm = (OP != OP_JACT) ? r[i][b] * (mlane * tb->imq[b]) : r[i][b];
+        const T sm = (OP != OP_JACT) ? r[i][b] * (mlane * te->imq[b]) : r[i][b];
         T r1 = b1 * sm;
         if (EP >= 1) r1 += a1 * E1[i][b];
         if (EP >= 2) r1 += c1 * E2[i][b];
@@ -273,16 +331,20 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
   }
 }
 
-// One field or a same-shape batch: workgroup L takes segment L % nseg of batch member L / nseg.
+// One field or a same-shape batch: workgroup L takes x-segment L % nxs of row segment
+// (L / nxs) % nseg of batch member L / (nxs nseg).
 template <typename T, int OP, int EP, int P>
-__global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args a, const FastTab<T, P>* __restrict__ tb,
-                                                           const T* __restrict__ u, const T* __restrict__ v,
-                                                           Epi epi, Coef in_scale) {
+__global__ __launch_bounds__(64 * Lay<P>::MAXW) void fast2d_kernel(Fast2Args a, const FastTab<T, P>* __restrict__ tb,
+                                                                   const T* __restrict__ u, const T* __restrict__ v,
+                                                                   Epi epi, Coef in_scale) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int L = logical_wg(blockIdx.x, a.nwg);
-  const int bm = L / a.nseg, seg = L - bm * a.nseg;
+  const int per = a.nseg * a.nxs;
+  const int bm = L / per, rem = L - bm * per, seg = rem / a.nxs, xs = rem - seg * a.nxs;
   Fast2Job g;
   g.Ey = a.Ey, g.nx = a.nx, g.ny = a.ny, g.nw = a.nw;
+  g.x0 = xs * a.nw * Lay<P>::EW;
+  g.xsplit = a.nxs > 1;
   g.y0 = seg * a.S;
   g.nrows = min(a.S, a.Ey - g.y0);
   g.nodes = a.nodes;
@@ -295,7 +357,7 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_kernel(Fast2Args a, const Fa
 // Problems of a batched set with the same x element count: workgroup b takes work item b, a row
 // segment of one packed problem (its constants read from the problem table).
 template <typename T, int OP, int EP, int P>
-__global__ __launch_bounds__(64 * MAXW) void fast2d_batch_kernel(const ProbDev* __restrict__ probs,
+__global__ __launch_bounds__(64 * Lay<P>::MAXW) void fast2d_batch_kernel(const ProbDev* __restrict__ probs,
                                                                  const Fast2Item* __restrict__ items,
                                                                  const FastTab<T, P>* __restrict__ tb,
                                                                  const T* __restrict__ u, const T* __restrict__ v,
@@ -304,7 +366,9 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_batch_kernel(const ProbDev* 
   const Fast2Item it = items[blockIdx.x];
   const ProbDev* __restrict__ pr = probs + it.prob;
   Fast2Job g;
-  g.Ey = pr->E[1], g.nx = pr->n[0], g.ny = pr->n[1], g.nw = pr->E[0] / EW;
+  g.Ey = pr->E[1], g.nx = pr->n[0], g.ny = pr->n[1], g.nw = blockDim.x >> 6;
+  g.x0 = it.x0;
+  g.xsplit = pr->E[0] > g.nw * Lay<P>::EW;
   g.y0 = it.y0;
   g.nrows = it.nrows;
   g.nodes = pr->nodes;
@@ -326,20 +390,33 @@ __global__ __launch_bounds__(64 * MAXW) void fast2d_batch_kernel(const ProbDev* 
 #define SEM_FAST2D_TARGET_J 256
 #endif
 
+// Wavefronts per workgroup for a row of ex elements: the whole row up to MAXW wavefronts, else
+// the largest divisor of the row's wavefront count that fits (x-segments of equal length).
+template <int P>
+int waves_of(int ex) {
+  int nw = ex / Lay<P>::EW;
+  if (nw <= Lay<P>::MAXW) return nw;
+  for (int d = Lay<P>::MAXW; d >= 1; --d)
+    if (nw % d == 0) return d;
+  return 1;
+}
+
+template <int P>
 Fast2Args make_args(const ProbDev& hp, const ProbDev* dprob, int op) {
   Fast2Args g;
   g.Ex = hp.E[0];
   g.Ey = hp.E[1];
   g.nx = hp.n[0];
   g.ny = hp.n[1];
-  g.nw = hp.E[0] / EW;
+  g.nw = waves_of<P>(hp.E[0]);
+  g.nxs = hp.E[0] / (g.nw * Lay<P>::EW);
   const int64_t target = op == OP_RHS ? SEM_FAST2D_TARGET_F : SEM_FAST2D_TARGET_J;
-  int64_t s = ((int64_t)hp.E[1] * hp.batch + target - 1) / target;
+  int64_t s = ((int64_t)hp.E[1] * hp.batch * g.nxs + target - 1) / target;
   if (s < 1) s = 1;
   if (s > hp.E[1]) s = hp.E[1];
   g.S = (int)s;
   g.nseg = (hp.E[1] + g.S - 1) / g.S;
-  g.nwg = g.nseg * hp.batch;
+  g.nwg = g.nseg * g.nxs * hp.batch;
   for (int k = 0; k < 2; ++k) {
     g.hh[k] = hp.hh[k];
     g.sc[k] = hp.sc[k];
@@ -354,7 +431,8 @@ template <typename T, int OP, int EP, int P>
 hipError_t launch_one(const Fast2Args& g, const FastTab<T, P>* tb, const T* u, const T* v, const Epi& epi,
                       Coef in_scale, hipStream_t s) {
   constexpr int NIN = OP == OP_RHS ? 1 : 2;
-  hipLaunchKernelGGL((fast2d_kernel<T, OP, EP, P>), dim3(g.nwg), dim3(64 * g.nw), lds_bytes<T>(NIN, g.nw), s, g, tb,
+  const size_t lds = lds_bytes<T, P>(NIN, g.nw);
+  hipLaunchKernelGGL((fast2d_kernel<T, OP, EP, P>), dim3(g.nwg), dim3(64 * g.nw), lds, s, g, tb,
                      u, v, epi, in_scale);
   return hipGetLastError();
 }
@@ -371,7 +449,7 @@ hipError_t launch_ep(const Fast2Args& g, const FastTab<T, P>* tb, const T* u, co
 template <typename T, int P>
 hipError_t run_fast2(const ProbDev& hp, const ProbDev* dprob, int op, const void* u, const void* v, const Epi& epi,
                      Coef in_scale, const void* dtab, hipStream_t s) {
-  const Fast2Args g = make_args(hp, dprob, op);
+  const Fast2Args g = make_args<P>(hp, dprob, op);
   const auto* tb = static_cast<const FastTab<T, P>*>(dtab);
   const T* uu = static_cast<const T*>(u);
   const T* vv = static_cast<const T*>(v);
@@ -383,7 +461,7 @@ hipError_t run_fast2(const ProbDev& hp, const ProbDev* dprob, int op, const void
 template <typename T, int OP, int P>
 hipError_t allow_lds_op() {
   constexpr int NIN = OP == OP_RHS ? 1 : 2;
-  const int bytes = (int)lds_bytes<T>(NIN, MAXW);
+  const int bytes = (int)lds_bytes<T, P>(NIN, Lay<P>::MAXW);
   const void* fns[6] = {reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 0, P>),
                         reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 1, P>),
                         reinterpret_cast<const void*>(&fast2d_kernel<T, OP, 2, P>),
@@ -403,7 +481,7 @@ hipError_t run_batch_op(const ProbDev* probs, const Fast2Item* items, int nitems
   constexpr int NIN = OP == OP_RHS ? 1 : 2;
   const int ep = (epi.o2 || epi.x2) ? 2 : (epi.x1 ? 1 : 0);
   const dim3 grid(nitems), block(64 * nw);
-  const size_t lds = lds_bytes<T>(NIN, nw);
+  const size_t lds = lds_bytes<T, P>(NIN, nw);
   if (ep == 0)
     hipLaunchKernelGGL((fast2d_batch_kernel<T, OP, 0, P>), grid, block, lds, s, probs, items, tb, u, v, epi, in_scale);
   else if (ep == 1)
@@ -446,17 +524,21 @@ void fill_tables(void* host) {
 }  // namespace
 
 bool fast2d_supported(const ProbDev& hp) {
-  // odd orders up to 7 (P = N + 1 even, at most the 8 lanes of an element); one workgroup spans a
-  // whole element row (8 elements per wavefront, at most 8 wavefronts); buffer offsets are 32-bit:
-  // one batch member (both components, FP64) must stay below 2 GiB
-  return hp.dim == 2 && (hp.N == 3 || hp.N == 5 || hp.N == 7) && hp.E[0] % EW == 0 && hp.E[0] >= EW &&
-         hp.E[0] <= EW * MAXW && hp.E[1] >= 1 && (int64_t)2 * hp.nodes * 8 < ((int64_t)1 << 31);
+  // odd orders 3, 5, 7 (P = N + 1 even, at most the 8 lanes of an element): one workgroup spans a
+  // whole element row (8 elements per wavefront, at most 8 wavefronts).  Order 9: 16 lanes and
+  // 4 elements per wavefront, rows of any multiple of 4 elements in x-segments of at most 16.
+  // Buffer offsets are 32-bit: one batch member (both components, FP64) must stay below 2 GiB.
+  const bool rows = (hp.N == 3 || hp.N == 5 || hp.N == 7) ? (hp.E[0] % 8 == 0 && hp.E[0] <= 64)
+                    : hp.N == 9                             ? hp.E[0] % 4 == 0
+                                                            : false;
+  return hp.dim == 2 && rows && hp.E[0] >= 1 && hp.E[1] >= 1 && (int64_t)2 * hp.nodes * 8 < ((int64_t)1 << 31);
 }
 
-// the tuned orders N = 3, 5, 7 have P = N + 1 = 4, 6, 8 points per line
+// the tuned orders N = 3, 5, 7, 9 have P = N + 1 = 4, 6, 8, 10 points per line
 #define SEM_FAST2D_ORDERS(X) \
   case 3: X(4);              \
   case 5: X(6);              \
+  case 9: X(10);             \
   default: X(8);
 
 size_t fast_table_bytes(int N) {
@@ -477,13 +559,15 @@ hipError_t fast2d_prepare(int N, int dtype) {
 #undef SEM_X
 }
 
-int fast2d_waves(const ProbDev& hp) { return hp.E[0] / EW; }
+int fast2d_waves(const ProbDev& hp) { return hp.N == 9 ? waves_of<10>(hp.E[0]) : waves_of<8>(hp.E[0]); }
+
+int fast2d_xsegments(const ProbDev& hp) { return hp.E[0] / (fast2d_waves(hp) * (hp.N == 9 ? 4 : 8)); }
 
 hipError_t launch_fast2d_batch(const ProbDev* dprobs, const Fast2Item* items, int nitems, int nw, int N, int op,
                                const void* u, const void* v, const Epi& epi, Coef in_scale, const void* dtables,
                                int dtype, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  if (nw < 1 || nw > MAXW) return hipErrorInvalidValue;
+  if (nw < 1 || nw > (N == 9 ? Lay<10>::MAXW : Lay<8>::MAXW)) return hipErrorInvalidValue;
 #define SEM_X(PV)                                                                                                   \
   return dtype == SEM_F64                                                                                           \
              ? run_batch<double, PV>(dprobs, items, nitems, nw, op, u, v, epi, in_scale, dtables, s)               \

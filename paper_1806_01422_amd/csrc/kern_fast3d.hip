@@ -24,25 +24,26 @@
 //      sweep.  The input plane is carried too, so each step loads 7 new planes.  A sweep split
 //      into z-segments instead starts each segment by recomputing the layer before it.
 //   x: inside a workgroup the shared face of wavefronts w and w + 1 is added through LDS.
-//   workgroup faces (F): a workgroup owns the nodes x in [28X, 28X + 28), y in [7ey, 7ey + 7)
-//      and completes them itself, so every output node is written once, by one lane, and no other
+//   workgroup faces: a workgroup owns the nodes x in [28X, 28X + 28), y in [7ey, 7ey + 7) and
+//      completes them itself, so every output node is written once, by one lane, and no other
 //      launch follows.  The element residual is a sum of per-direction terms, each a function of
 //      the element's line through the node along that direction only (Sec. 3.3: the operators
-//      are sums over directions j of D_j^T(.) and pointwise D_j terms).  At a node of the lower
-//      face (y = 7ey) the missing element row below shares the own element's x- and z-lines
-//      (GLL weights w_0 = w_7, equal element sizes), so its x- and z-terms equal the own ones:
-//      they are doubled, and only its y-term is formed, from its y-line (line_end_terms).  The
-//      left face (x = 28X, wavefront 0) is completed the same way with the left element's
-//      x-line; at the corner line both rules apply (the diagonal element's terms are the doubled
-//      y-term of the lower and x-term of the left element).  The upper and right faces are left
-//      to the workgroups that own them.
-//   workgroup faces (J v, J^T, whose neighbour lines would push the kernel past its registers):
-//      the workgroup writes its finished nodes to the output and, to a face buffer, its partial
-//      sums of the lower y-row (y = 7ey), its contributions to the upper y-row and upper x-column
-//      (owned by the neighbours), and the first 32-byte sector of each interior row (x in
-//      [28X, 28X + 4): the x = 28X node still lacks the left neighbour's part).  fast3d_fixup
-//      adds the parts, applies the inverse mass and the epilogue, and writes those nodes as whole
-//      row segments and whole sectors, so no 32-byte sector of the output is written twice.
+//      are sums over directions j of D_j^T(.) and pointwise D_j terms; for J v and J^T the same
+//      holds with the second input's line beside the state's).  At a node of the lower face
+//      (y = 7ey) the missing element row below shares the own element's x- and z-lines (GLL
+//      weights w_0 = w_7, equal element sizes), so its x- and z-terms equal the own ones: they
+//      are doubled, and only its y-term is formed, from its y-lines (line_end_terms).  The left
+//      face (x = 28X, wavefront 0) is completed the same way with the left element's x-lines; at
+//      the corner line both rules apply (the diagonal element's terms are the doubled y-term of
+//      the lower and x-term of the left element).  The upper and right faces are left to the
+//      workgroups that own them.
+//   workgroup faces of the segmented J^T (FP32, two wavefronts per SIMD, no registers for the
+//      neighbours' lines): the workgroup writes its finished nodes to the output and, to a face
+//      buffer, its partial sums of the lower y-row (y = 7ey), its contributions to the upper
+//      y-row and upper x-column (owned by the neighbours), and the first 32-byte sector of each
+//      interior row (x in [28X, 28X + 4): the x = 28X node still lacks the left neighbour's
+//      part).  fast3d_fixup adds the parts and applies the epilogue, and writes those nodes as
+//      whole row segments and whole sectors, so no 32-byte sector of the output is written twice.
 #include "fast_common.h"
 
 namespace sem {
@@ -86,8 +87,10 @@ template <typename T, int OP, int EP, bool SEG>
 __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                      const T* __restrict__ u, const T* __restrict__ v,
                                                      T* __restrict__ face, Epi epi, Coef in_scale) {
-  // F completes the workgroup faces in the kernel; J v and J^T go through the face buffer
-  constexpr bool CMPL = OP == OP_RHS;
+  // The workgroup faces are completed in the kernel, except by the segmented J^T (FP32), whose
+  // register budget (two wavefronts per SIMD) leaves no room for the neighbours' lines: it goes
+  // through the face buffer and fast3d_fixup
+  constexpr bool CMPL = !(SEG && OP == OP_JACT);
   constexpr bool HASV = OP != OP_RHS;
   __shared__ T sU[4][3][512];
   __shared__ T sV[4][HASV ? 3 : 1][HASV ? 512 : 1];
@@ -192,6 +195,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   // mass and epilogue for the owned nodes, raw sums to the face-buffer slots (J v, J^T).  Every
   // lane issues the same stores; inactive ones drop theirs.
   auto emit = [&](int ez, const T (&Zv)[3][8], int c_lo, int c_hi, const T (&E1)[3][7], const T (&E2)[3][7]) {
+    const auto te = phase_ptr(tb);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
         const int z = 7 * ez + c;  // < nz: c < 7
         const T r = Zv[i][c];
         const uint32_t no = (uint32_t)((i * g.nodes + z * plane + orow) * sizeof(T));
-        const T sm = (OP != OP_JACT) ? r * (mlane * tb->imq[c]) : r;
+        const T sm = (OP != OP_JACT) ? r * (mlane * te->imq[c]) : r;
         T r1 = b1 * sm;
         if (EP >= 1) r1 += a1 * E1[i][c];
         if (EP >= 2) r1 += c1 * E2[i][c];
@@ -250,12 +254,13 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   };
   auto lines_node = [&](bool ylow, const T* __restrict__ tile, bool scale, T (&L)[3][8]) {
     const int t = ylow ? tix(l0, 0, l1) : tix(0, l0, l1);
+    const auto tl = phase_ptr(tb);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       L[i][7] = tile[i * 512 + t];
       if (scale) {
 #pragma unroll
-        for (int n = 0; n < 7; ++n) L[i][n] *= zin * tb->imq[n];
+        for (int n = 0; n < 7; ++n) L[i][n] *= zin * tl->imq[n];
       }
     }
   };
@@ -273,8 +278,10 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   // the neighbouring elements' lines of the next layer to process (the left ones: wavefront 0),
   // loaded at the end of the previous step and used right after the tile is staged
   T YU[3][8], YV[3][8], XU[3][8], XV[3][8];
+  // F prefetches them a step ahead; J v and J^T, which hold twice the lines (both inputs), load
+  // them where they are used (prefetched, they would push those kernels past their registers)
   auto load_neighbours = [&](int ez) {
-    if constexpr (!CMPL) return;
+    if constexpr (!CMPL || HASV) return;
     load_lines(true, ez, r_u, YU);
     if constexpr (HASV) load_lines(true, ez, r_v, YV);
     if (wave == 0) {
@@ -293,10 +300,11 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 #pragma unroll
     for (int i = 0; i < 3; ++i) wlast[i] = cv[i][7];
     if constexpr (OP == OP_JACT) {
+      const auto ts = phase_ptr(tb);
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) cv[i][c] *= zin * tb->imq[c];
+        for (int c = 0; c < 8; ++c) cv[i][c] *= zin * ts->imq[c];
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -315,7 +323,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 #pragma unroll
           for (int c = 0; c < 8; ++c) Xr[c] = cv[i][c];
         },
-        om, K1z * fz, K2z * fz, tb,
+        om, K1z * fz, K2z * fz, phase_ptr(tb),
         [&](int i, const T (&P)[8]) {
 #pragma unroll
           for (int c = 0; c < 8; ++c) tQ[i * 512 + tix(l0, l1, c)] = P[c];
@@ -327,17 +335,25 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
     wave_sync();
     {
       T low[3];
+      if constexpr (HASV) {
+        load_lines(true, ez, r_u, YU);
+        load_lines(true, ez, r_v, YV);
+      }
       lines_node(true, tU, false, YU);
       if constexpr (HASV) lines_node(true, tV, OP == OP_JACT, YV);
-      line_end_terms<T, OP, 3>(1, YU, YV, om[7], K1y * fy, K2y * fy, tb, low);
+      line_end_terms<T, OP, 3>(1, YU, YV, om[7], K1y * fy, K2y * fy, phase_ptr(tb), low);
 #pragma unroll
       for (int i = 0; i < 3; ++i) tQ[i * 512 + tix(l0, 0, l1)] += low[i];
     }
     if (wave == 0) {
       T low[3];
+      if constexpr (HASV) {
+        load_lines(false, ez, r_u, XU);
+        load_lines(false, ez, r_v, XV);
+      }
       lines_node(false, tU, false, XU);
       if constexpr (HASV) lines_node(false, tV, OP == OP_JACT, XV);
-      line_end_terms<T, OP, 3>(0, XU, XV, om[7], K1x * fx, K2x * fx, tb, low);
+      line_end_terms<T, OP, 3>(0, XU, XV, om[7], K1x * fx, K2x * fx, phase_ptr(tb), low);
       wave_sync();
 #pragma unroll
       for (int i = 0; i < 3; ++i) tQ[i * 512 + tix(0, l0, l1)] += low[i];
@@ -364,7 +380,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 #pragma unroll
           for (int q = 0; q < 8; ++q) Xr[q] = tV[i * 512 + tix(l0, q, l1)];
         },
-        om, K1y * fy, K2y * fy, tb,
+        om, K1y * fy, K2y * fy, phase_ptr(tb),
         [&](int i, const T (&P)[8]) {
           // read the 8 values first, then write: one LDS round trip per component instead of
           // one per value (the compiler cannot prove the swizzled addresses distinct)
@@ -388,7 +404,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 #pragma unroll
           for (int q = 0; q < 8; ++q) Xr[q] = tV[i * 512 + tix(q, l0, l1)];
         },
-        om, K1x * fx, K2x * fx, tb,
+        om, K1x * fx, K2x * fx, phase_ptr(tb),
         [&](int i, const T (&P)[8]) {
           T qv[8];
 #pragma unroll
@@ -447,10 +463,10 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 // Completes, for every workgroup (X, ey), component and grid plane z, the nodes of its lower
 // y-row (own partial plus the lower neighbour's upper-y contribution) and of the first sectors of
 // its interior rows (own value plus, at x = 28X, the left neighbour's upper-x contribution); the
-// node (28X, 7ey) also receives the diagonal neighbour's corner.  Then the inverse mass (F, J v)
-// and the epilogue.  One thread per 32-byte output sector (4 nodes along x); blockIdx.x is
+// node (28X, 7ey) also receives the diagonal neighbour's corner.  Then the epilogue (J^T has no
+// inverse mass to apply).  One thread per 32-byte output sector (4 nodes along x); blockIdx.x is
 // (workgroup, component), blockIdx.y a range of (z, sector) pairs, blockIdx.z the batch member.
-template <typename T, bool DIV>
+template <typename T>
 __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                     const T* __restrict__ face, Epi epi) {
   const int t = blockIdx.y * 256 + threadIdx.x;
@@ -479,11 +495,6 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
     s[0] += rec(Xm + g.NX * ey, O_UX, W_UX)[yl];
   }
   const double dt = g.prob->dt;
-  if (DIV) {
-    const T m = tb->imq[yl] * tb->imq[z % NQ] * (T)g.ihhh;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) s[q] *= m * tb->imq[(xl0 + q) % NQ];
-  }
   const int64_t o = (int64_t)blockIdx.z * 3 * g.nodes + i * g.nodes +
                     ((int64_t)z * g.ny + 7 * ey + yl) * g.nx + 7 * WX * X + xl0;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
@@ -514,6 +525,9 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
 int z_segments(const ProbDev& hp, int op, bool f32) {
   return (f32 && (op == OP_RHS || op == OP_JACT) && hp.E[2] >= 4) ? 2 : 1;
 }
+
+// the launches that go through the face buffer and fast3d_fixup: the segmented J^T
+bool fast3d_face_buffer(const ProbDev& hp, int op, bool f32) { return op == OP_JACT && z_segments(hp, op, f32) > 1; }
 
 FastArgs make_args(const ProbDev& hp, const ProbDev* dprob, int nseg) {
   FastArgs g;
@@ -580,12 +594,9 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
 #undef SEM_FAST_EP
 #undef SEM_FAST_LAUNCH
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || op == OP_RHS) return e;  // F completes its faces in the kernel
+  if (e != hipSuccess || !fast3d_face_buffer(hp, op, sizeof(T) == 4)) return e;  // faces completed in the kernel
   const dim3 fgrid((unsigned)(g.NWG * 3), (unsigned)((g.nz * FSEC + 255) / 256), hp.batch);
-  if (op == OP_JACT)
-    hipLaunchKernelGGL((fast3d_fixup<T, false>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
-  else
-    hipLaunchKernelGGL((fast3d_fixup<T, true>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
+  hipLaunchKernelGGL((fast3d_fixup<T>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
   return hipGetLastError();
 }
 
@@ -598,7 +609,8 @@ bool fast3d_supported(const ProbDev& hp) {
 }
 
 
-int64_t fast3d_face_values(const ProbDev& hp) {
+int64_t fast3d_face_values(const ProbDev& hp, int dtype) {
+  if (!fast3d_face_buffer(hp, OP_JACT, dtype == SEM_F32)) return 0;
   return (int64_t)hp.batch * (hp.E[0] / WX) * hp.E[1] * 3 * hp.n[2] * FROWS;
 }
 

@@ -320,7 +320,7 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
       size_t k1 = k;
       int64_t rows = 0;
       for (; k1 < tid.size() && fast2d_waves(tmp[tid[k1]]) == nw && tmp[tid[k1]].N == N; ++k1)
-        rows += tmp[tid[k1]].E[1];
+        rows += (int64_t)tmp[tid[k1]].E[1] * fast2d_xsegments(tmp[tid[k1]]);
       const int SEG = (int)std::max<int64_t>(1, std::min<int64_t>(4, rows / 256));
       std::vector<Fast2Item> its;
       for (; k < k1; ++k) {
@@ -328,7 +328,9 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
         p.item0 = p.loff = p.node0 = 0;  // unused: no element items, scratch or summation items
         const int t = (int)os.hp.size();
         os.hp.push_back(p);
-        for (int y0 = 0; y0 < p.E[1]; y0 += SEG) its.push_back({t, y0, std::min(SEG, p.E[1] - y0), 0});
+        const int nxs = fast2d_xsegments(p), xw = p.E[0] / nxs;
+        for (int y0 = 0; y0 < p.E[1]; y0 += SEG)
+          for (int xs = 0; xs < nxs; ++xs) its.push_back({t, y0, std::min(SEG, p.E[1] - y0), xs * xw});
       }
       OpSet::TunedGroup g;
       g.N = N;
@@ -395,7 +397,7 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     fast_fill_tables(descs[0].order, host.data());
     if ((rc = os.fast_tab.alloc(host.size()))) return rc;
     HIPCHK(hipMemcpy(os.fast_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
-    if (os.fast == 3 && (rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts))) return rc;
+    if (os.fast == 3 && (rc = os.face.alloc(fast3d_face_values(os.hp[0], os.dtype) * os.ts))) return rc;
     if (os.fast == 2) HIPCHK(fast2d_prepare(descs[0].order, os.dtype));
   }
   return os.finalize();

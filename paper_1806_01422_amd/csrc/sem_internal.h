@@ -102,7 +102,7 @@ void gll_tables(int N, double* xi, double* w, double* D);
 // workgroups still read the input nodes that a workgroup has finished.  Both take the device
 // table of their order (fast_fill_tables).
 bool fast3d_supported(const ProbDev& hp);
-int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch (J v, J^T)
+int64_t fast3d_face_values(const ProbDev& hp, int dtype);  // face-buffer values per launch (0: none used)
 bool fast2d_supported(const ProbDev& hp);
 // lets the 2-D kernels of order N and dtype use their workgroup LDS (more than the default limit)
 hipError_t fast2d_prepare(int N, int dtype);
@@ -145,9 +145,10 @@ struct Fast2Item {
   int32_t prob;   // index into the problem table
   int32_t y0;     // first element row of the segment
   int32_t nrows;  // element rows of the segment
-  int32_t pad;
+  int32_t x0;     // first element column of the segment (rows split into x-segments: order 9)
 };
-int fast2d_waves(const ProbDev& hp);
+int fast2d_waves(const ProbDev& hp);      // wavefronts per workgroup
+int fast2d_xsegments(const ProbDev& hp);  // workgroups per element row
 hipError_t launch_fast2d_batch(const ProbDev* dprobs, const Fast2Item* items, int nitems, int nw, int N, int op,
                                const void* u, const void* v, const Epi& epi, Coef in_scale, const void* dtables,
                                int dtype, hipStream_t s);

@@ -75,10 +75,14 @@ CASES = [
     # 2-D kernel: one or several wavefronts per workgroup, one element row, ragged row segments
     (2, 7, [8, 1]), (2, 7, [8, 2]), (2, 7, [8, 3]), (2, 7, [16, 5]), (2, 7, [24, 2]),
     (2, 5, [8, 1]), (2, 5, [16, 3]), (2, 5, [40, 2]), (2, 3, [8, 2]), (2, 3, [24, 5]), (2, 3, [64, 1]),
+    # order 9 with an x element count that is a multiple of 4 runs the tuned 2-D kernel with 16
+    # lanes per element, a whole row of up to 16 elements per workgroup (longer rows: see
+    # test_tuned_2d_order9_segments)
+    (2, 9, [4, 3]), (2, 9, [12, 5]), (2, 9, [16, 2]),
 ]
 
 TUNED = {(2, 7, (8, 1)): 2, (2, 7, (64, 3)): 2, (3, 7, (4, 1, 1)): 3, (3, 7, (4, 4, 4)): 3, (2, 7, (5, 3)): 0,
-         (2, 7, (72, 2)): 0, (2, 9, (8, 2)): 0, (3, 7, (3, 2, 4)): 0, (2, 5, (8, 2)): 2, (2, 3, (16, 1)): 2,
+         (2, 7, (72, 2)): 0, (2, 9, (8, 2)): 2, (2, 9, (64, 2)): 2, (2, 9, (6, 2)): 0, (2, 9, (20, 1)): 2, (3, 7, (3, 2, 4)): 0, (2, 5, (8, 2)): 2, (2, 3, (16, 1)): 2,
          (2, 4, (8, 2)): 0, (2, 6, (8, 2)): 0, (2, 1, (8, 2)): 0, (3, 5, (4, 1, 1)): 0}
 
 
@@ -104,10 +108,13 @@ def test_kernel_path_selection(P):
 # segments (the second one ragged for odd E_z), each recomputing the layer before it
 @pytest.mark.parametrize("dim,N,E", [(1, 8, [16]), (2, 7, [5, 3]), (3, 7, [3, 2, 4]), (3, 5, [2, 2, 3]),
                                      (3, 7, [4, 2, 3]), (2, 7, [8, 3]), (2, 5, [8, 3]), (3, 7, [4, 1, 4]),
-                                     (3, 7, [4, 2, 5]), (3, 7, [8, 1, 7])])
+                                     (3, 7, [4, 2, 5]), (3, 7, [8, 1, 7]), (2, 9, [16, 3]), (2, 9, [32, 2])])
 def test_operators_fp32(P, dim, N, E):
     note(f"operators fp32 dim={dim} N={N} E={E}")
-    m, c = make(P, dim, N, E, nu=0.02, dtype=torch.float32)
+    # order 9 on the unit square puts FP32's own rounding floor at 1e-4 and above for these rows
+    # (tests/test_rounding_floor.py); stretched along x it is about 2e-5
+    L = [E[0] / 4.0, 1.0] if N == 9 else None
+    m, c = make(P, dim, N, E, nu=0.02, L=L, dtype=torch.float32)
     u, v, w = fields(m, 9)
     U, V, W = gpu(u, torch.float32), gpu(v, torch.float32), gpu(w, torch.float32)
     assert rel(c.rhs(U), m.rhs(u)) < 1e-4
@@ -129,10 +136,10 @@ def test_rk4_fp32_3d(P, E):
     assert rel(lam, m.rk4_adjoint(ck_ref, dt, n, K, w)) < 1e-4
 
 
-@pytest.mark.parametrize("dim,N", [(1, 4), (2, 4), (3, 4), (3, 7)])
-def test_batched_fields(P, dim, N):
-    note(f"same-shape batch dim={dim} N={N}")
-    m, c = make(P, dim, N, [4, 2, 3][:dim], nu=0.03, batch=3)
+@pytest.mark.parametrize("dim,N,E", [(1, 4, [4]), (2, 4, [4, 2]), (3, 4, [4, 2, 3]), (3, 7, [4, 2, 3])])
+def test_batched_fields(P, dim, N, E):
+    note(f"same-shape batch dim={dim} N={N} E={E}")
+    m, c = make(P, dim, N, E, nu=0.03, batch=3)
     u, v, w = fields(m, 11)
     U, V, W = gpu(u), gpu(v), gpu(w)
     assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
@@ -160,6 +167,24 @@ def test_batched_fields_fp32_segments(P):
 def test_tuned_2d_wide_rows(P, E, L):
     note(f"tuned 2-D kernel, wide rows E={E} L={L}")
     m, c = make(P, 2, 7, E, nu=0.02, L=L)
+    assert c.path == 2
+    u, v, w = fields(m, 7)
+    U, V, W = gpu(u), gpu(v), gpu(w)
+    assert rel(c.rhs(U), m.rhs(u)) < TOL_APPLY
+    assert rel(c.jac_vec(U, V), m.jac_vec(u, v)) < TOL_APPLY
+    assert rel(c.jact_vec(U, W), m.jact_vec(u, w)) < TOL_APPLY
+
+
+# Order 9 on rows longer than 16 elements: x-segments of one workgroup each whose left faces are
+# completed in the kernel (2 and 4 segments of 16 elements, 5 segments of 4 for 20 elements), on
+# domains stretched along x.  On the unit square the operator's FP64 rounding floor there is
+# above the bound: 2.2e-12 for 32 x 3 and 9.1e-12 for 64 x 1 elements at nu = 0.02
+# (tests/test_rounding_floor.py::test_floor_of_order9_wide_rows).
+@pytest.mark.parametrize("E,L,batch", [([32, 3], [4.0, 1.0], 1), ([64, 1], [8.0, 1.0], 1), ([20, 2], [3.0, 1.0], 1),
+                                       ([32, 3], [4.0, 1.0], 3)])
+def test_tuned_2d_order9_segments(P, E, L, batch):
+    note(f"tuned 2-D kernel, order 9, x-segments E={E} L={L} batch={batch}")
+    m, c = make(P, 2, 9, E, nu=0.02, L=L, batch=batch)
     assert c.path == 2
     u, v, w = fields(m, 7)
     U, V, W = gpu(u), gpu(v), gpu(w)
@@ -335,12 +360,16 @@ def test_trajectory_stored_tail(P, scheme):
 
 @pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1),
                                            (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2),
-                                           (2, 7, [8, 3], 2), (2, 7, [8, 1], 1), (2, 5, [8, 2], 2)])
+                                           (2, 7, [8, 3], 2), (2, 7, [8, 1], 1), (2, 5, [8, 2], 2),
+                                           (2, 9, [32, 2], 2), (2, 9, [8, 3], 1)])
 def test_rk4_forward_adjoint(P, dim, N, E, batch):
     note(f"RK4 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
-    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    # order 9 takes a 4x smaller step (RK4 at 2e-3 is unstable there: the oracle diverges) and the
+    # 32-element rows a domain stretched along x
+    L = [E[0] / 8.0, 1.0] if N == 9 and E[0] > 16 else None
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch, L=L)
     u, _, w = fields(m, 17)
-    dt, n, K = 2e-3, 20, 5
+    dt, n, K = (5e-4 if N == 9 else 2e-3), 20, 5
     uT_ref, ck_ref = m.rk4_forward(u, dt, n, K)
     assert np.isfinite(uT_ref).all()
     uT, ck = c.rk4_forward(gpu(u), dt, n, K)
@@ -562,6 +591,19 @@ def test_c4_full_horizon_finite_differences(P):
 def batch_problems(count):
     probs = wl.c5_problems(count)
     return [dict(dim=2, order=p.N, elems=(p.E, p.E), length=(1.0, 1.0), nu=p.nu, dt=p.dt) for p in probs], probs
+
+
+def mixed_batch_specs(count):
+    # the batched set's recipe (all of it on the tuned 2-D kernel) plus problems that run the
+    # generic element and summation kernels (other orders and x element counts), so that the
+    # persistent launch has work
+    specs, _ = batch_problems(count)
+    extra = [(6, (6, 5)), (8, (8, 8)), (4, (10, 6)), (9, (6, 6)), (7, (12, 4))]
+    for i, (N, E) in enumerate(extra):
+        nu = 10.0 ** (-2.5 - 0.3 * i)
+        specs.append(dict(dim=2, order=N, elems=E, length=(1.0, 1.0), nu=nu,
+                          dt=min(wl.stable_dt(2, N, max(E), 1.0, nu), wl.C5_T_MAX / wl.C5_STEPS)))
+    return specs
 
 
 def test_batch_operators_match_single(P):
@@ -1036,16 +1078,16 @@ def test_nonfinite_detection(P):
 
 
 def test_batch_launch_shapes_and_autotune(P):
-    note("batched uneven set (C5 recipe, 20 problems): launch shapes bitwise equal, autotune")
-    specs, probs = batch_problems(20)
+    note("batched uneven set (C5 recipe, 20 problems, and 5 generic ones): launch shapes bitwise equal, autotune")
+    specs = mixed_batch_specs(20)
     B = P.Batch(specs)
     u = B.empty()
     w = B.empty()
-    for i, (s, p) in enumerate(zip(specs, probs)):
+    for i, s in enumerate(specs):
         m = oracle.Mesh(2, s["order"], list(s["elems"]), [1.0, 1.0], s["nu"])
         xs = [m.coords(k) for k in range(2)]
-        B.view(u, i).copy_(gpu(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, p.ic_seed)[None]))
-        B.view(w, i).copy_(gpu(wl.normal_field(m.shape, p.target_seed)))
+        B.view(u, i).copy_(gpu(wl.fourier_field(xs, [1.0, 1.0], wl.C5_K, 41 + i)[None]))
+        B.view(w, i).copy_(gpu(wl.normal_field(m.shape, 1041 + i)))
     B.configure(True, 1024)
     f0, j0 = B.rhs(u), B.jact_vec(u, w)
     u1, _ = B.rk4_forward(u, 6, 0)
@@ -1065,7 +1107,7 @@ def test_configure_right_after_unsynchronised_integration(P):
     # configure drops the captured step graphs; with graph launches of an integration still in
     # flight it must wait for them first.  Results after the change equal those before, bitwise.
     note("batched set: configure right after an unsynchronised rk4_forward / rk4_adjoint")
-    specs, _ = batch_problems(20)
+    specs = mixed_batch_specs(20)
     B = P.Batch(specs)
     x = gpu(wl.normal_field((B.total,), 31)) * 0.01
     B.configure(False, 0)

@@ -64,15 +64,19 @@ def gll_ext(N):
 
 
 class Ext2D:
-    """2-D periodic mesh of E_x x E_y elements of order N on [0, L_x] x [0, L_y], long double."""
+    """2-D periodic mesh of E_x x E_y elements of order N on [0, L_x] x [0, L_y], evaluated in the
+    working precision ft (long double by default)."""
 
-    def __init__(self, N, E, L, nu):
-        self.N, self.E, self.nu = N, E, LD(nu)
+    def __init__(self, N, E, L, nu, ft=LD):
+        # ft: the working precision (long double for the floor itself; float32 evaluates the same
+        # formulas with tables and inputs rounded from long double, the floor of an FP32 apply)
+        self.N, self.E, self.ft = N, E, ft
         _, w, D = gll_ext(N)
-        self.D = D
         h = [LD(L[d]) / E[d] for d in range(2)]
-        self.sc = [2 / h[0], 2 / h[1]]
-        self.om = (h[0] / 2) * (h[1] / 2) * np.outer(w, w)  # [b][a]
+        self.nu = ft(nu)
+        self.D = D.astype(ft)
+        self.sc = [ft(2 / h[0]), ft(2 / h[1])]
+        self.om = ((h[0] / 2) * (h[1] / 2) * np.outer(w, w)).astype(ft)  # [b][a]
         n = [E[0] * N, E[1] * N]
         self.n = n
         self.gx = (np.arange(E[0])[:, None] * N + np.arange(N + 1)[None, :]) % n[0]  # [ex][a]
@@ -84,7 +88,7 @@ class Ext2D:
         return f[self.gy[:, None, :, None], self.gx[None, :, None, :]]
 
     def scatter(self, t):
-        out = np.zeros((self.n[1], self.n[0]), dtype=LD)
+        out = np.zeros((self.n[1], self.n[0]), dtype=self.ft)
         np.add.at(out, (self.gy[:, None, :, None], self.gx[None, :, None, :]), t)
         return out
 
@@ -97,7 +101,7 @@ class Ext2D:
             self.sc[1] * np.einsum("mb,...ma->...ba", self.D, V)
 
     def rhs(self, u):
-        U = [self.gather(u[c].astype(LD)) for c in range(2)]
+        U = [self.gather(u[c].astype(self.ft)) for c in range(2)]
         f = []
         for i in range(2):
             G = [self.d(j, U[i]) for j in range(2)]
@@ -106,8 +110,8 @@ class Ext2D:
         return np.stack(f)
 
     def jact_vec(self, u, w):
-        U = [self.gather(u[c].astype(LD)) for c in range(2)]
-        Z = [self.gather(w[c].astype(LD) / self.M) for c in range(2)]
+        U = [self.gather(u[c].astype(self.ft)) for c in range(2)]
+        Z = [self.gather(w[c].astype(self.ft) / self.M) for c in range(2)]
         out = []
         for l in range(2):
             R = -sum(self.dt(j, self.om * (self.nu * self.d(j, Z[l]) + U[j] * Z[l])) for j in range(2))
@@ -191,3 +195,37 @@ def test_floor_of_the_2d_apply_workload():
     f_floor, jt_floor = floor(7, (64, 64), (1.0, 1.0), 1e-3, u, w)
     print(f"64^2 N=7 nu=1e-3: F floor {f_floor:.2e}, J^T floor {jt_floor:.2e}")
     assert f_floor < 1e-12 and jt_floor < 1e-12
+
+
+def test_floor_of_order9_wide_rows():
+    # order 9 with 32 x 3 and 64 x 1 elements on the unit square at nu = 0.02 (x-segmented rows of
+    # the tuned 2-D kernel): the floor exceeds 1e-12; on domains stretched along x it falls well
+    # below, which is where the GPU tests of those rows run
+    for E, L, lo, hi in (((32, 3), (1.0, 1.0), 1e-12, 5e-12), ((64, 1), (1.0, 1.0), 4e-12, 2e-11),
+                         ((32, 3), (4.0, 1.0), 0.0, 5e-13), ((64, 1), (8.0, 1.0), 0.0, 5e-13)):
+        m = oracle.Mesh(2, 9, E, L, 0.02)
+        xs = [m.coords(k) for k in range(2)]
+        u = wl.fourier_field(xs, L, 3, 7)
+        w = wl.normal_field(m.shape, 207)[0]
+        f_floor, jt_floor = floor(9, E, L, 0.02, u, w)
+        print(f"order 9 {E} L={L}: F floor {f_floor:.2e}, J^T floor {jt_floor:.2e}")
+        assert lo < f_floor < hi, (E, L, f_floor)
+        assert jt_floor < hi, (E, L, jt_floor)
+
+
+def test_fp32_floor_of_order9_rows():
+    # The same formulas in FP32 (tables and inputs rounded from long double) on the order-9 meshes
+    # of the FP32 GPU tests, at nu = 0.02: on the unit square 16 x 3 and 32 x 2 elements put the
+    # FP32 floor at 1e-4 and above (rounding the input alone moves F by about 1e-4), so no FP32
+    # apply can be held to 1e-4 there; stretched to [0, 4] x [0, 1] and [0, 8] x [0, 1] it falls to
+    # about 2e-5, which is where the GPU tests hold them to 1e-4
+    for E, L, lo, hi in (((16, 3), (1.0, 1.0), 1e-4, 1e-3), ((32, 2), (1.0, 1.0), 5e-4, 5e-3),
+                         ((16, 3), (4.0, 1.0), 0.0, 4e-5), ((32, 2), (8.0, 1.0), 0.0, 4e-5)):
+        m = oracle.Mesh(2, 9, E, L, 0.02)
+        xs = [m.coords(k) for k in range(2)]
+        u = wl.fourier_field(xs, L, 3, 9)
+        ref = Ext2D(9, E, L, 0.02).rhs(u)
+        f32 = Ext2D(9, E, L, 0.02, ft=np.float32).rhs(u.astype(np.float32))
+        f32_floor = rel(f32, ref)
+        print(f"order 9 {E} L={L}: FP32 F floor {f32_floor:.2e}")
+        assert lo < f32_floor < hi, (E, L, f32_floor)
