@@ -37,13 +37,13 @@
 //      the corner line both rules apply (the diagonal element's terms are the doubled y-term of
 //      the lower and x-term of the left element).  The upper and right faces are left to the
 //      workgroups that own them.
-//   workgroup faces of the segmented J^T (FP32, two wavefronts per SIMD, no registers for the
-//      neighbours' lines): the workgroup writes its finished nodes to the output and, to a face
-//      buffer, its partial sums of the lower y-row (y = 7ey), its contributions to the upper
+//   workgroup faces of the plain J v and J^T and of the segmented FP32 J^T (face_buffer_variant):
+//      the workgroup writes its finished nodes to the output and, to a face buffer, its partial sums of the lower y-row (y = 7ey), its contributions to the upper
 //      y-row and upper x-column (owned by the neighbours), and the first 32-byte sector of each
 //      interior row (x in [28X, 28X + 4): the x = 28X node still lacks the left neighbour's
-//      part).  fast3d_fixup adds the parts and applies the epilogue, and writes those nodes as
-//      whole row segments and whole sectors, so no 32-byte sector of the output is written twice.
+//      part).  fast3d_fixup adds the parts and applies M^{-1} (J v) and the epilogue, and writes
+//      those nodes as whole row segments and whole sectors, so no 32-byte sector of the output is
+//      written twice.
 #include "fast_common.h"
 
 namespace sem {
@@ -79,6 +79,19 @@ struct FastArgs {
 // 32-bit accesses with all 64 lanes at once).
 __device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b ^ c) << 3) + (a ^ b); }
 
+// The variants that leave their workgroup faces to the face buffer and fast3d_fixup:
+//   the plain J v and J^T (no epilogue): completing the faces in the kernel takes them exactly as
+//     long (the neighbour lines, loaded where they are used, expose their latency) and re-reads
+//     the neighbour rows from beyond the L2, 1.44 GB per J^T apply against 1.14 GB with the face
+//     buffer;
+//   the segmented J^T (FP32): its register budget (two wavefronts per SIMD) leaves no room for the
+//     neighbours' lines.
+// With a stage epilogue J v and J^T complete their faces: the fixup would read the epilogue
+// operands of its nodes as scattered sectors, and there the in-kernel completion is faster.
+constexpr bool face_buffer_variant(int op, int ep, bool seg) {
+  return (op != OP_RHS && ep == 0) || (seg && op == OP_JACT);
+}
+
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
 // 2 = o1 = a1 x1 + c1 x2 + b1 s and (when o2 is given) o2 = a2 x2 + c2 x1 + b2 s.
 // SEG: the z-sweep split into g.nseg segments (else one sweep closed by the periodic wrap), for
@@ -87,10 +100,8 @@ template <typename T, int OP, int EP, bool SEG>
 __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                      const T* __restrict__ u, const T* __restrict__ v,
                                                      T* __restrict__ face, Epi epi, Coef in_scale) {
-  // The workgroup faces are completed in the kernel, except by the segmented J^T (FP32), whose
-  // register budget (two wavefronts per SIMD) leaves no room for the neighbours' lines: it goes
-  // through the face buffer and fast3d_fixup
-  constexpr bool CMPL = !(SEG && OP == OP_JACT);
+  // The workgroup faces are completed in the kernel, except by the variants of face_buffer_variant
+  constexpr bool CMPL = !face_buffer_variant(OP, EP, SEG);
   constexpr bool HASV = OP != OP_RHS;
   __shared__ T sU[4][3][512];
   __shared__ T sV[4][HASV ? 3 : 1][HASV ? 512 : 1];
@@ -463,10 +474,10 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 // Completes, for every workgroup (X, ey), component and grid plane z, the nodes of its lower
 // y-row (own partial plus the lower neighbour's upper-y contribution) and of the first sectors of
 // its interior rows (own value plus, at x = 28X, the left neighbour's upper-x contribution); the
-// node (28X, 7ey) also receives the diagonal neighbour's corner.  Then the epilogue (J^T has no
-// inverse mass to apply).  One thread per 32-byte output sector (4 nodes along x); blockIdx.x is
+// node (28X, 7ey) also receives the diagonal neighbour's corner.  Then the inverse mass (J v) and
+// the epilogue.  One thread per 32-byte output sector (4 nodes along x); blockIdx.x is
 // (workgroup, component), blockIdx.y a range of (z, sector) pairs, blockIdx.z the batch member.
-template <typename T>
+template <typename T, bool DIV>
 __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>* __restrict__ tb,
                                                     const T* __restrict__ face, Epi epi) {
   const int t = blockIdx.y * 256 + threadIdx.x;
@@ -495,6 +506,11 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
     s[0] += rec(Xm + g.NX * ey, O_UX, W_UX)[yl];
   }
   const double dt = g.prob->dt;
+  if (DIV) {
+    const T m = tb->imq[yl] * tb->imq[z % NQ] * (T)g.ihhh;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s[q] *= m * tb->imq[(xl0 + q) % NQ];
+  }
   const int64_t o = (int64_t)blockIdx.z * 3 * g.nodes + i * g.nodes +
                     ((int64_t)z * g.ny + 7 * ey + yl) * g.nx + 7 * WX * X + xl0;
   const T a1 = coef<T>(epi.a1, dt), b1 = coef<T>(epi.b1, dt), a2 = coef<T>(epi.a2, dt), b2 = coef<T>(epi.b2, dt);
@@ -526,8 +542,10 @@ int z_segments(const ProbDev& hp, int op, bool f32) {
   return (f32 && (op == OP_RHS || op == OP_JACT) && hp.E[2] >= 4) ? 2 : 1;
 }
 
-// the launches that go through the face buffer and fast3d_fixup: the segmented J^T
-bool fast3d_face_buffer(const ProbDev& hp, int op, bool f32) { return op == OP_JACT && z_segments(hp, op, f32) > 1; }
+// whether a launch goes through the face buffer and fast3d_fixup
+bool fast3d_face_buffer(const ProbDev& hp, int op, int ep, bool f32) {
+  return face_buffer_variant(op, ep, z_segments(hp, op, f32) > 1);
+}
 
 FastArgs make_args(const ProbDev& hp, const ProbDev* dprob, int nseg) {
   FastArgs g;
@@ -594,9 +612,12 @@ hipError_t run_fast(const ProbDev& hp, const ProbDev* dprob, int op, const void*
 #undef SEM_FAST_EP
 #undef SEM_FAST_LAUNCH
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !fast3d_face_buffer(hp, op, sizeof(T) == 4)) return e;  // faces completed in the kernel
+  if (e != hipSuccess || !fast3d_face_buffer(hp, op, ep, sizeof(T) == 4)) return e;  // faces completed in the kernel
   const dim3 fgrid((unsigned)(g.NWG * 3), (unsigned)((g.nz * FSEC + 255) / 256), hp.batch);
-  hipLaunchKernelGGL((fast3d_fixup<T>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
+  if (op == OP_JACT)
+    hipLaunchKernelGGL((fast3d_fixup<T, false>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
+  else
+    hipLaunchKernelGGL((fast3d_fixup<T, true>), fgrid, dim3(256), 0, s, g, tb, fc, epi);
   return hipGetLastError();
 }
 
@@ -609,8 +630,7 @@ bool fast3d_supported(const ProbDev& hp) {
 }
 
 
-int64_t fast3d_face_values(const ProbDev& hp, int dtype) {
-  if (!fast3d_face_buffer(hp, OP_JACT, dtype == SEM_F32)) return 0;
+int64_t fast3d_face_values(const ProbDev& hp) {
   return (int64_t)hp.batch * (hp.E[0] / WX) * hp.E[1] * 3 * hp.n[2] * FROWS;
 }
 

@@ -102,7 +102,7 @@ void gll_tables(int N, double* xi, double* w, double* D);
 // workgroups still read the input nodes that a workgroup has finished.  Both take the device
 // table of their order (fast_fill_tables).
 bool fast3d_supported(const ProbDev& hp);
-int64_t fast3d_face_values(const ProbDev& hp, int dtype);  // face-buffer values per launch (0: none used)
+int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch (plain J v, J^T)
 bool fast2d_supported(const ProbDev& hp);
 // lets the 2-D kernels of order N and dtype use their workgroup LDS (more than the default limit)
 hipError_t fast2d_prepare(int N, int dtype);
