@@ -99,6 +99,12 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
   constexpr int NIN = HASV ? 2 : 1;
   constexpr int N = P - 1;
   constexpr int LPE = Lay<P>::LPE, EW = Lay<P>::EW, TC = Lay<P>::TC;
+  // the coefficient table of a phase: a fresh pointer per phase (phase_ptr), except for J^T, which
+  // measured 4-5% faster reading the table through the kernel argument
+  auto tph = [&]() {
+    if constexpr (OP == OP_JACT) return tb;
+    else return phase_ptr(tb);
+  };
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nw = g.nw;
@@ -180,7 +186,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
 #pragma unroll
     for (int i = 0; i < 2; ++i) vlast[i] = cv[i][N];
     if constexpr (OP == OP_JACT) {
-      const auto ts = phase_ptr(tb);
+      const auto ts = tph();
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -194,7 +200,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
         if constexpr (HASV) tV[i * TC + tix2<P>(e, a, b)] = cv[i][b];
       }
     T r[2][P];
-    const auto ty = phase_ptr(tb);
+    const auto ty = tph();
     map_contrib<T, OP, 2, P>(
         1,
         [&](int i, T (&X)[P]) {
@@ -227,7 +233,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
     // x-terms at its last point are added at a = 0 (its lines' last point is the own node).
     T lowX[2] = {0, 0};
     if (SPLITS && lface) {
-      const auto tl = phase_ptr(tb);
+      const auto tl = tph();
       T XU[2][P], XV[2][P];
       const uint32_t rb = (uint32_t)((int64_t)((N * ey + l0) % g.ny) * g.nx * sizeof(T));
       const int xl0 = (g.x0 == 0 ? g.nx : N * g.x0) - N;  // first column of the left element
@@ -252,7 +258,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
       }
       line_end_terms<T, OP, 2, P>(0, XU, XV, omf * tl->w[N], K1x, K2x, tl, lowX);
     }
-    const auto tx = phase_ptr(tb);
+    const auto tx = tph();
     map_contrib<T, OP, 2, P>(
         0,
         [&](int i, T (&X)[P]) {
@@ -308,7 +314,7 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
     // ---- outputs: grid rows N ey .. N ey + N - 1, lanes a < N (inverse mass for F and J v); all
     // epilogue operands are read first (o2 may alias x2)
     const uint32_t vo = (st && a < N) ? lcol : OOB;
-    const auto te = phase_ptr(tb);
+    const auto te = tph();
     T E1[2][N], E2[2][N];
 #pragma unroll
     for (int i = 0; i < 2; ++i)

@@ -361,7 +361,7 @@ def test_trajectory_stored_tail(P, scheme):
 @pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1),
                                            (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2),
                                            (2, 7, [8, 3], 2), (2, 7, [8, 1], 1), (2, 5, [8, 2], 2),
-                                           (2, 9, [32, 2], 2), (2, 9, [8, 3], 1)])
+                                           (2, 9, [32, 2], 2), (2, 9, [8, 3], 1), (3, 7, [8, 2, 3], 1)])
 def test_rk4_forward_adjoint(P, dim, N, E, batch):
     note(f"RK4 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
     # order 9 takes a 4x smaller step (RK4 at 2e-3 is unstable there: the oracle diverges) and the
