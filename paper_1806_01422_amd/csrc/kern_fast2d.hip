@@ -73,9 +73,11 @@ __device__ __forceinline__ int tix2(int e, int a, int b) {
 
 // LDS per workgroup: per wavefront a tile of NIN * 2 components x TC points, then the x-face
 // exchange between wavefronts [step parity][wavefront][component][b].
+// Order 9 adds a copy of the coefficient table (read from LDS by J^T; see fast2d_body).
 template <typename T, int P>
 constexpr size_t lds_bytes(int nin, int nw) {
-  return sizeof(T) * ((size_t)nw * nin * 2 * Lay<P>::TC + (size_t)2 * nw * 2 * Lay<P>::LPE);
+  return sizeof(T) * ((size_t)nw * nin * 2 * Lay<P>::TC + (size_t)2 * nw * 2 * Lay<P>::LPE) +
+         (P > 8 ? sizeof(FastTab<T, P>) : 0);
 }
 
 // The work of one workgroup: a row segment of one field, or of one x-segment of it (all values
@@ -99,10 +101,27 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
   constexpr int NIN = HASV ? 2 : 1;
   constexpr int N = P - 1;
   constexpr int LPE = Lay<P>::LPE, EW = Lay<P>::EW, TC = Lay<P>::TC;
-  // the coefficient table of a phase: a fresh pointer per phase (phase_ptr), except for J^T, which
-  // measured 4-5% faster reading the table through the kernel argument
+  // The coefficient table of a phase.  Orders up to 7: a fresh pointer per phase (phase_ptr),
+  // except for J^T, which measured 4-5% faster reading the table through the kernel argument.
+  // Order 9: the two 5 x 5 blocks alone (100 scalar registers) overflow the scalar file, and the
+  // compiler then parks the coefficients in vector-register lanes and restores each with two lane
+  // reads before every use (over half of the loop's VALU instructions).  J^T copies the table into
+  // LDS once and reads each coefficient with a broadcast LDS read into a vector register: no lane
+  // moves, at one wavefront per SIMD instead of two, 10% faster.  F and J v measured the same time
+  // either way (their register-held coefficients cost the second wavefront), so they keep the
+  // scalar reads.
+  constexpr bool LTAB = P > 8 && OP == OP_JACT;
+  FastTab<T, P>* ltab = nullptr;
+  if constexpr (LTAB) {
+    ltab = reinterpret_cast<FastTab<T, P>*>(lds + (size_t)g.nw * NIN * 2 * TC + (size_t)2 * g.nw * 2 * LPE);
+    const T* __restrict__ src = reinterpret_cast<const T*>(tb);
+    T* __restrict__ dst = reinterpret_cast<T*>(ltab);
+    for (int k = threadIdx.x; k < (int)(sizeof(FastTab<T, P>) / sizeof(T)); k += blockDim.x) dst[k] = src[k];
+    __syncthreads();
+  }
   auto tph = [&]() {
-    if constexpr (OP == OP_JACT) return tb;
+    if constexpr (LTAB) return static_cast<const FastTab<T, P>*>(ltab);
+    else if constexpr (OP == OP_JACT) return tb;
     else return phase_ptr(tb);
   };
 
