@@ -26,6 +26,7 @@
 //      the carry into the segment's first grid row is complete and every node is written once,
 //      by one lane, as part of whole row segments of 8N nodes.
 #include "fast_common.h"
+#include "fast_consts.h"  // written by the build (gen/fast_consts_gen.hip)
 
 namespace sem {
 namespace {
@@ -104,12 +105,18 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
   // The coefficient table of a phase.  Orders up to 7: a fresh pointer per phase (phase_ptr),
   // except for J^T, which measured 4-5% faster reading the table through the kernel argument.
   // Order 9: the two 5 x 5 blocks alone (100 scalar registers) overflow the scalar file, and the
-  // compiler then parks the coefficients in vector-register lanes and restores each with two lane
-  // reads before every use (over half of the loop's VALU instructions).  J^T copies the table into
-  // LDS once and reads each coefficient with a broadcast LDS read into a vector register: no lane
-  // moves, at one wavefront per SIMD instead of two, 10% faster.  F and J v measured the same time
-  // either way (their register-held coefficients cost the second wavefront), so they keep the
-  // scalar reads.
+  // compiler then parks the coefficients of a run-time table in vector-register lanes and
+  // restores each with two lane reads before every use (over half of the loop's VALU
+  // instructions).
+  //   F and J v (FP64) take the coefficients as compile-time constants (FastConst, written by the
+  //     build from the same table routine): each is formed with two scalar moves next to its use,
+  //     and the kernel keeps two wavefronts per SIMD (order-9 F 112 -> 82 us).
+  //   J^T copies the table into LDS once and reads each coefficient with a broadcast LDS read
+  //     into a vector register: no lane moves, at one wavefront per SIMD instead of two, 10%
+  //     faster; with the constants it needs one register more than two wavefronts allow and is
+  //     slower than from LDS.
+  //   FP32 keeps the run-time table (its scalar file holds the single-precision blocks).
+  constexpr bool CTAB = P == 10 && sizeof(T) == 8 && OP != OP_JACT;
   constexpr bool LTAB = P > 8 && OP == OP_JACT;
   FastTab<T, P>* ltab = nullptr;
   if constexpr (LTAB) {
@@ -119,8 +126,10 @@ __device__ __forceinline__ void fast2d_body(const Fast2Job& g, const FastTab<T, 
     for (int k = threadIdx.x; k < (int)(sizeof(FastTab<T, P>) / sizeof(T)); k += blockDim.x) dst[k] = src[k];
     __syncthreads();
   }
+  static constexpr FastConst<10> ctab{};
   auto tph = [&]() {
-    if constexpr (LTAB) return static_cast<const FastTab<T, P>*>(ltab);
+    if constexpr (CTAB) return &ctab;
+    else if constexpr (LTAB) return static_cast<const FastTab<T, P>*>(ltab);
     else if constexpr (OP == OP_JACT) return tb;
     else return phase_ptr(tb);
   };
