@@ -276,6 +276,16 @@ int sem_set_check_finite(sem_ctx ctx, int32_t on);
 /* Message of the last failure on the calling thread ("" if none).  Valid until the next call. */
 const char* sem_last_error(void);
 
+/* Diagnostic, outside the operator path: the FP64 rates of this GPU's matrix cores
+ * (v_mfma_f64_16x16x4f64) and vector units (v_fma_f64), each alone and both interleaved in one
+ * instruction stream of 4096 x 256 threads, `iters` loop iterations each.  This is the measurement
+ * behind contracting the element lines (Sec. 3.3, sum factorisation) with vector FMAs.  Writes
+ * tflops[0] = matrix cores alone, [1] = vector units alone, [2] and [3] = the matrix and vector
+ * parts of the interleaved run (host array of 4, TFLOP/s).  Allocates and frees an 8 MiB device
+ * buffer; `stream` may be NULL (the default stream); synchronises it.  SEM_ERR_ARG for a NULL
+ * result or iters < 1. */
+int sem_probe_fp64_rates(void* stream, int32_t iters, double* tflops);
+
 /* ---------------------------------------------------------------------------------------------
  * Batched uneven problems: `count` independent problems of possibly different dim-2 shapes,
  * orders, viscosities and step sizes, packed back to back in one device array (problem p

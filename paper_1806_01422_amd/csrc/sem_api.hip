@@ -1336,6 +1336,38 @@ static int check_steps(double dt, int32_t nsteps, int32_t K, bool need_k) {
   return SEM_OK;
 }
 
+int sem_probe_fp64_rates(void* stream, int32_t iters, double* tflops) {
+  if (!tflops || iters < 1) return fail(SEM_ERR_ARG, "sem_probe_fp64_rates: null result or iters < 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevBuf out;
+  if (int rc = out.alloc(fp64_probe_values() * sizeof(double))) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const double waves = (double)fp64_probe_values() / 64;
+  const double fm = waves * iters * fp64_probe_mfma_flops_per_wave_iter();
+  const double fv = waves * iters * fp64_probe_valu_flops_per_wave_iter();
+  int rc = SEM_OK;
+  float ms[3] = {0, 0, 0};
+  for (int mode = 0; mode < 3 && rc == SEM_OK; ++mode) {
+    hipError_t he = launch_fp64_probe(mode, static_cast<double*>(out.p), iters, s);  // warm-up
+    if (he == hipSuccess) he = hipEventRecord(e0, s);
+    if (he == hipSuccess) he = launch_fp64_probe(mode, static_cast<double*>(out.p), iters, s);
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms[mode], e0, e1);
+    if (he != hipSuccess) rc = fail(SEM_ERR_HIP, "sem_probe_fp64_rates: %s", hipGetErrorString(he));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  tflops[0] = fm / (ms[0] * 1e-3) / 1e12;
+  tflops[1] = fv / (ms[1] * 1e-3) / 1e12;
+  tflops[2] = fm / (ms[2] * 1e-3) / 1e12;
+  tflops[3] = fv / (ms[2] * 1e-3) / 1e12;
+  return SEM_OK;
+}
+
 int sem_set_check_finite(sem_ctx c, int32_t on) {
   if (!c) return fail(SEM_ERR_ARG, "null context");
   c->check_finite = on != 0;

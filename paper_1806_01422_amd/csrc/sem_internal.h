@@ -102,7 +102,14 @@ void gll_tables(int N, double* xi, double* w, double* D);
 // workgroups still read the input nodes that a workgroup has finished.  Both take the device
 // table of their order (fast_fill_tables).
 bool fast3d_supported(const ProbDev& hp);
-int64_t fast3d_face_values(const ProbDev& hp);  // face-buffer values per launch (plain J v, J^T)
+int64_t fast3d_face_values(const ProbDev& hp);
+
+// FP64 rate diagnostic (kern_probe.hip): mode 0 matrix cores, 1 vector FMAs, 2 both interleaved;
+// `out` holds fp64_probe_values() doubles.
+int64_t fp64_probe_values();
+hipError_t launch_fp64_probe(int mode, double* out, int iters, hipStream_t s);
+double fp64_probe_mfma_flops_per_wave_iter();
+double fp64_probe_valu_flops_per_wave_iter();  // face-buffer values per launch (plain J v, J^T)
 bool fast2d_supported(const ProbDev& hp);
 // lets the 2-D kernels of order N and dtype use their workgroup LDS (more than the default limit)
 hipError_t fast2d_prepare(int N, int dtype);

@@ -123,6 +123,7 @@ _SIGS = {
     "sem_batch_configure": [_vp, _i32, _i32],
     "sem_batch_set_stream": [_vp, _vp],
     "sem_batch_autotune": [_vp, ctypes.POINTER(_f64)],
+    "sem_probe_fp64_rates": [_vp, _i32, _vp],
 }
 EXPORTED = tuple(_SIGS)
 
@@ -449,6 +450,15 @@ class Context:
         _call(lib().sem_rk_adjoint_revolve(self._h, code, _ptr(ckpt), float(dt), int(nsteps), int(snaps), _ptr(lam),
                                            _ptr(work)))
         return lam
+
+
+def probe_fp64_rates(iters=2000):
+    """FP64 TFLOP/s of the matrix cores and the vector units of the current GPU, alone and
+    interleaved in one instruction stream (a diagnostic; see sem_probe_fp64_rates)."""
+    out = (_f64 * 4)()
+    _call(lib().sem_probe_fp64_rates(_stream(), int(iters), out))
+    return {"mfma_alone": out[0], "valu_alone": out[1], "interleaved_mfma": out[2], "interleaved_valu": out[3],
+            "interleaved_total": out[2] + out[3]}
 
 
 def revolve_plan(nsteps, snaps):

@@ -53,6 +53,17 @@ def test_last_error_without_gpu(libsem):
     assert b"descriptor" in libsem.sem_last_error()
 
 
+def test_probe_rejects_bad_arguments_without_gpu(libsem):
+    # argument errors are reported before any device call
+    fn = libsem.sem_probe_fp64_rates
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+    out = (ctypes.c_double * 4)()
+    assert fn(None, 0, out) == -1
+    assert fn(None, 10, None) == -1
+    libsem.sem_last_error.restype = ctypes.c_char_p
+    assert b"sem_probe_fp64_rates" in libsem.sem_last_error()
+
+
 def test_lattice_and_fourier_recipe():
     assert len(wl.lattice(1, 3)) == 6
     assert len(wl.lattice(2, 1)) == 4

@@ -1183,3 +1183,14 @@ def test_lifecycle_releases_device_memory(P):
     free1 = torch.cuda.mem_get_info()[0]
     note(f"  free before {free0 >> 20} MiB, after {free1 >> 20} MiB")
     assert free0 - free1 < (64 << 20), (free0, free1)
+
+
+def test_fp64_rate_probe(P):
+    # the diagnostic entry point runs and reports plausible rates (below the 78.6 TFLOP/s FP64
+    # peak, with margin for the clock); its figures themselves are measurements, not parity
+    note("FP64 rate probe")
+    r = P.probe_fp64_rates(iters=200)
+    for k in ("mfma_alone", "valu_alone", "interleaved_mfma", "interleaved_valu"):
+        assert 0 < r[k] < 100, (k, r[k])
+    assert r["interleaved_total"] < 100
+
