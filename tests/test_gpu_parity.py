@@ -331,13 +331,15 @@ def test_c1_trajectory_and_gradient(P):
 
 
 @pytest.mark.parametrize("scheme", ["rk4", "rk3"])
-def test_trajectory_stored_tail(P, scheme):
+@pytest.mark.parametrize("N", [7, 9])
+def test_trajectory_stored_tail(P, scheme, N):
     # the last stored_tail segments keep their stage states in the forward sweep: the same values
     # as the checkpointed sweep (the same launches on the same states), and the oracle's gradient
-    note(f"trajectory with stored tail segments ({scheme}), 2-D 8x3 N=7, batch 2")
-    m, c = make(P, 2, 7, [8, 3], nu=0.01, batch=2)
+    # (order 9 runs the tuned 2-D kernel with compile-time coefficients, at a 4x smaller step)
+    note(f"trajectory with stored tail segments ({scheme}), 2-D 8x3 N={N}, batch 2")
+    m, c = make(P, 2, N, [8, 3], nu=0.01, batch=2)
     u, _, w = fields(m, 23)
-    dt, n, K = 2e-3, 20, 5
+    dt, n, K = (2e-3 if N == 7 else 5e-4), 20, 5
     ref = None
     for tail in (0, 1, 3, 4):
         x = gpu(u).requires_grad_(True)
