@@ -204,7 +204,9 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
 
   // Write planes c in [c_lo, c_hi) of element layer ez from the summed z-map values Zv: inverse
   // mass and epilogue for the owned nodes, raw sums to the face-buffer slots (J v, J^T).  Every
-  // lane issues the same stores; inactive ones drop theirs.
+  // lane issues the same stores; inactive ones drop theirs, each at its own offset beyond the
+  // range (with bit 31 set; a batch member and its face buffer stay below 2 GiB), so that the
+  // compiler keeps every dropped store as a distinct access.
   auto emit = [&](int ez, const T (&Zv)[3][8], int c_lo, int c_hi, const T (&E1)[3][7], const T (&E2)[3][7]) {
     const auto te = phase_ptr(tb);
 #pragma unroll
@@ -219,11 +221,11 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
         T r1 = b1 * sm;
         if (EP >= 1) r1 += a1 * E1[i][c];
         if (EP >= 2) r1 += c1 * E2[i][c];
-        bstore(r_o1, (own && inc) ? no : OOB, r1);
-        if (EP >= 2) bstore(r_o2, (own && inc) ? no : OOB, a2 * E2[i][c] + c2 * E1[i][c] + b2 * sm);
+        bstore(r_o1, (own && inc) ? no : (OOB | no), r1);
+        if (EP >= 2) bstore(r_o2, (own && inc) ? no : (OOB | no), a2 * E2[i][c] + c2 * E1[i][c] + b2 * sm);
         if constexpr (!CMPL) {
           const uint32_t fb = (uint32_t)((flane + ((int64_t)i * g.nz + z) * fw) * sizeof(T));
-          bstore(r_fb, (fo >= 0 && inc) ? fb : OOB, r);
+          bstore(r_fb, (fo >= 0 && inc) ? fb : (OOB | fb), r);
         }
       }
   };
@@ -302,6 +304,19 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   };
   load_neighbours(zfirst);
   T carry[3] = {0, 0, 0}, first0[3] = {0, 0, 0};
+  {
+    // The store sequence of a step, with every store dropped.  Loads and stores share one
+    // completion counter that drains in issue order, and the compiler's wait for a load in the
+    // loop allows only the memory operations issued after it on every path into the loop.  On
+    // the back edge the previous step's stores follow the layer and neighbour loads; issuing the
+    // same sequence before the loop lets those waits leave the stores in flight (else every step
+    // would first wait for the previous step's stores to complete).
+    T Z0[3][8] = {}, E0[3][7] = {};
+    // after the loads above (the asm may read the inputs, so their loads cannot move below it)
+    asm volatile("" ::"s"(ub), "s"(HASV ? vb : ub) : "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    emit(zfirst, Z0, 0, 0, E0, E0);
+  }
 
   for (int k = 0; k < nstep; ++k) {
     const int ez = wrap ? k : (k == 0 ? zfirst : z0 + k - 1);
@@ -427,6 +442,13 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
     // epilogue operands of this layer: issued before the barrier so that their latency overlaps it
     T E1[3][7], E2[3][7];
     load_epi(ez, E1, E2, c_lo, c_hi);
+    // The next layer's neighbour lines (F; the last step loads one layer more).  Loads and stores
+    // share one completion counter that drains in issue order, so lines loaded after this step's
+    // stores would wait for them too: the plain apply issues them here, before its stores (F
+    // 278 -> 268 us on the 32^3 field).  The stage variants issue them after their stores: here,
+    // behind the epilogue operands, they made an RK4 step 4% slower.
+    const int ezn = ez + 1 < g.Ez ? ez + 1 : 0;
+    if constexpr (EP == 0) load_neighbours(ezn);
     // ---- x-direction summation inside the workgroup: wavefront w's face a = 7 is wavefront
     // w + 1's face a = 0 (double-buffered by step parity: one barrier per step)
     const int par = k & 1;
@@ -457,7 +479,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
     }
     // ---- outputs (with one segment, plane c = 0 of layer 0 waits for the periodic wrap)
     emit(ez, Zv, c_lo, c_hi, E1, E2);
-    load_neighbours(ez + 1 < g.Ez ? ez + 1 : 0);  // the last step loads one layer more
+    if constexpr (EP != 0) load_neighbours(ezn);
   }
   // periodic wrap along z: the carried plane of the last layer is plane c = 0 of layer 0
   if (wrap) {
