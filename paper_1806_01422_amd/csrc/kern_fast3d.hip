@@ -51,6 +51,7 @@ namespace {
 
 using namespace fast;
 constexpr int WX = 4;  // elements per workgroup along x, one per wavefront
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 // Face buffer of one batch member: four regions, each [workgroup][component][grid plane z][width]
 // so that every region is read by one neighbour's fixup as a run contiguous in z.
 //   LY  own lower y-row y = 7ey, x-local 0..27 (partial sums)             width 28
@@ -252,10 +253,30 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   // left element's x-lines in the x-map (xleft), for layer ez, of one input field (r_u or r_v).
   // lines_node fills point 7 from the tile; J^T scales its second input to Z = M^{-1} w like
   // the tile's.
+  // An x-line's points 0..6 lie in one grid row, one row per lane.  FP64 reads them with three
+  // 16-byte loads and one 8-byte load per lane instead of seven 8-byte ones: a load touches a cache
+  // line per lane, so fewer, wider loads cost the cache less (F 271 -> 263 us on the 32^3 field).
+  // FP32 keeps one load per point: its 16- and 12-byte loads compiled to wrong results.
   auto load_lines = [&](bool ylow, int ez, __amdgpu_buffer_rsrc_t r, T (&L)[3][8]) {
     int zc = 7 * ez + l1;
     if (zc >= g.nz) zc -= g.nz;
     const uint32_t lane_off = (uint32_t)(((int64_t)zc * plane + (ylow ? xcol_a : (int64_t)yrow_b * g.nx)) * sizeof(T));
+    if constexpr (sizeof(T) == 8) {
+      if (!ylow) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const uint32_t uni = (uint32_t)(((int64_t)i * g.nodes + xl0) * sizeof(T));
+#pragma unroll
+          for (int n = 0; n < 6; n += 2) {
+            const u32x4_t q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)lane_off, (int)(uni + 8 * n), 0);
+            L[i][n] = __builtin_bit_cast(double, u32x2_t{q.x, q.y});
+            L[i][n + 1] = __builtin_bit_cast(double, u32x2_t{q.z, q.w});
+          }
+          L[i][6] = bload_s<T>(r, lane_off, uni + 48);
+        }
+        return;
+      }
+    }
 #pragma unroll
     for (int n = 0; n < 7; ++n) {
 #pragma unroll
