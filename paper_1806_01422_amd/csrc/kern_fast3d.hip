@@ -595,19 +595,21 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   const T* x1 = epi.x1 ? static_cast<const T*>(epi.x1) + o : nullptr;
   T* o2 = epi.o2 ? static_cast<T*>(epi.o2) + o : nullptr;
   const T* x2 = epi.x2 ? static_cast<const T*>(epi.x2) + o : nullptr;
-  // all operands first: a store may alias a later operand, so the loads must not wait behind it
-  T v1[4], v2[4];
+  // all operands first: a store may alias a later operand, so the loads must not wait behind it.
+  // The sector is 32-byte aligned (28X and x-local 4k nodes, rows of 7 E_x nodes with 4 | E_x),
+  // so each operand moves as one vector (16-byte accesses) instead of four scalar ones.
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  const T4 zero = {0, 0, 0, 0};
+  const T4 v1 = x1 ? *reinterpret_cast<const T4*>(x1) : zero;
+  const T4 v2 = x2 ? *reinterpret_cast<const T4*>(x2) : zero;
+  T4 r1, r2;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    v1[q] = x1 ? x1[q] : (T)0;
-    v2[q] = x2 ? x2[q] : (T)0;
+    r1[q] = b1 * s[q] + a1 * v1[q] + c1 * v2[q];
+    r2[q] = b2 * s[q] + a2 * v2[q] + c2 * v1[q];
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    T r1 = b1 * s[q] + a1 * v1[q] + c1 * v2[q];
-    if (o2) o2[q] = b2 * s[q] + a2 * v2[q] + c2 * v1[q];
-    o1[q] = r1;
-  }
+  if (o2) *reinterpret_cast<T4*>(o2) = r2;
+  *reinterpret_cast<T4*>(o1) = r1;
 }
 
 // z-segments per column: the FP32 F and J^T kernels (54 and 78 KB of LDS, at most 256 registers)
