@@ -261,7 +261,11 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     tmp[i].off = off[i];
   }
   os.total_vals = off[count];
-  os.fast = !allow_fast || count != 1 ? 0 : fast3d_supported(tmp[0]) ? 3 : fast2d_supported(tmp[0]) ? 2 : 0;
+  // the tuned 3-D kernel addresses a batch member and its face buffer with 32-bit byte offsets
+  // and drops accesses by setting bit 31, so both must stay below 2 GiB
+  const bool fast3 = count == 1 && fast3d_supported(tmp[0]) &&
+                     fast3d_face_values(tmp[0]) / tmp[0].batch * 8 < ((int64_t)1 << 31);
+  os.fast = !allow_fast || count != 1 ? 0 : fast3 ? 3 : fast2d_supported(tmp[0]) ? 2 : 0;
   // a batched 2-D set runs its problems of order 3, 5 or 7 with 8 | E_x <= 64 on the tuned kernel:
   // they go after every order class, so the generic launches cover a prefix of the table
   std::vector<char> is_tuned(count, 0);
