@@ -596,9 +596,10 @@ __global__ __launch_bounds__(256) void fast3d_fixup(FastArgs g, const FastTab<T>
   T* o2 = epi.o2 ? static_cast<T*>(epi.o2) + o : nullptr;
   const T* x2 = epi.x2 ? static_cast<const T*>(epi.x2) + o : nullptr;
   // all operands first: a store may alias a later operand, so the loads must not wait behind it.
-  // The sector is 32-byte aligned (28X and x-local 4k nodes, rows of 7 E_x nodes with 4 | E_x),
-  // so each operand moves as one vector (16-byte accesses) instead of four scalar ones.
-  typedef T T4 __attribute__((ext_vector_type(4)));
+  // A sector is 4 contiguous nodes, so each operand moves as one vector (16-byte accesses)
+  // instead of four scalar ones.  The vector type assumes only the element's alignment; within
+  // a field the sectors are 32-byte aligned (28X and x-local 4k nodes, rows of 7 E_x nodes).
+  typedef T T4 __attribute__((ext_vector_type(4), aligned(sizeof(T))));
   const T4 zero = {0, 0, 0, 0};
   const T4 v1 = x1 ? *reinterpret_cast<const T4*>(x1) : zero;
   const T4 v2 = x2 ? *reinterpret_cast<const T4*>(x2) : zero;
