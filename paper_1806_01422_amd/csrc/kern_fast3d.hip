@@ -260,7 +260,8 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   // An x-line's points 0..6 lie in one grid row, one row per lane.  FP64 reads them with three
   // 16-byte loads and one 8-byte load per lane instead of seven 8-byte ones: a load touches a cache
   // line per lane, so fewer, wider loads cost the cache less (F 271 -> 263 us on the 32^3 field).
-  // FP32 keeps one load per point: its 16- and 12-byte loads compiled to wrong results.
+  // FP32 keeps one load per point: a 16- plus 12-byte version gave wrong results (cause not
+  // traced; F's FP32 lines now go through the LDS tile below).
   auto load_lines = [&](bool ylow, int ez, __amdgpu_buffer_rsrc_t r, T (&L)[3][8]) {
     int zc = 7 * ez + l1;
     if (zc >= g.nz) zc -= g.nz;
