@@ -332,16 +332,15 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
       for (int i = 0; i < 3; ++i) XT[i][c] = bload_s<T>(r_u, xt_lane, (uint32_t)((i * g.nodes + zc * plane) * sizeof(T)));
     }
   };
-  // F prefetches them a step ahead; J v and J^T, which hold twice the lines (both inputs), load
-  // them where they are used (prefetched, they would push those kernels past their registers)
+  // F prefetches them a step ahead.  J v and J^T hold twice the lines (both inputs): they
+  // prefetch the lower element's state lines (RK4 adjoint with stored stages 2.03 -> 1.98 ms per
+  // step) and load the second input's lines and wavefront 0's left lines where they are used
+  // (prefetched too, they spilled 17-139 registers and ran slower)
   auto load_neighbours = [&](int ez) {
-    if constexpr (!CMPL || HASV) return;
+    if constexpr (!CMPL) return;
     load_lines(true, ez, r_u, YU);
-    if constexpr (HASV) load_lines(true, ez, r_v, YV);
-    if (wave == 0) {
-      if constexpr (LTILE) load_left_block(ez);
-      else load_lines(false, ez, r_u, XU);
-      if constexpr (HASV) load_lines(false, ez, r_v, XV);
+    if constexpr (LTILE) {
+      if (wave == 0) load_left_block(ez);
     }
   };
   load_neighbours(zfirst);
@@ -403,10 +402,7 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
     wave_sync();
     {
       T low[3];
-      if constexpr (HASV) {
-        load_lines(true, ez, r_u, YU);
-        load_lines(true, ez, r_v, YV);
-      }
+      if constexpr (HASV) load_lines(true, ez, r_v, YV);
       lines_node(true, tU, false, YU);
       if constexpr (HASV) lines_node(true, tV, OP == OP_JACT, YV);
       line_end_terms<T, OP, 3>(1, YU, YV, om[7], K1y * fy, K2y * fy, phase_ptr(tb), low);
