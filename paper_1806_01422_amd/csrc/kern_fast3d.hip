@@ -314,8 +314,8 @@ __global__ __launch_bounds__(256, SEG ? 2 : 1) void fast3d_kernel(FastArgs g, co
   const int zfirst = wrap ? 0 : (z0 == 0 ? g.Ez - 1 : z0 - 1);
   T cu[3][8], cv[3][8];
   load_z(zfirst, 0, cu, cv);
-  // the neighbouring elements' lines of the next layer to process (the left ones: wavefront 0),
-  // loaded at the end of the previous step and used right after the tile is staged
+  // the neighbouring elements' lines through the layer's face nodes (the left ones: wavefront
+  // 0), used right after the tile is staged; load_neighbours issues those loaded a step ahead
   T YU[3][8], YV[3][8], XU[3][8], XV[3][8];
   // F (wavefront 0): the left element's columns x = xl0 + a (a < 7; lanes a = 7 repeat a = 6) of
   // the workgroup's rows, in the z-map (lane (a, b), register c).  Loaded like the own layer (8
