@@ -161,7 +161,8 @@ int sem_rk_adjoint(sem_ctx ctx, int32_t scheme, const void* ckpt, double dt, int
      fused updates.  Bitwise equal to sem_rk_adjoint with the stage states stored
      (SEM_ADJ_STORE).
    With nsteps = 0 the stage buffer may be NULL; lam (and u) pass through unchanged.  An unknown
-   scheme, a non-positive dt or aliased buffers are SEM_ERR_ARG. */
+   scheme, a non-positive dt or aliased buffers are SEM_ERR_ARG; sem_rk_adjoint_stored updates lam
+   in place, so lam overlapping the stage states is SEM_ERR_ARG too. */
 int sem_rk_stages_bytes(sem_ctx ctx, int32_t scheme, int32_t nsteps, int64_t* bytes);
 int sem_rk_forward_stored(sem_ctx ctx, int32_t scheme, void* u, double dt, int32_t nsteps, void* stages);
 int sem_rk_adjoint_stored(sem_ctx ctx, int32_t scheme, const void* stages, double dt, int32_t nsteps, void* lam);

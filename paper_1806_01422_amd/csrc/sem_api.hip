@@ -492,15 +492,17 @@ struct Integrator {
     const void* st[2] = {b(A2), b(A3)};
     return enqueue_adjoint_jt_rk3(s, b(USTATE), st);
   }
-  // the J^T part of the RK-3 adjoint step from u and its stage states st = {U2, U3}
-  hipError_t enqueue_adjoint_jt_rk3(hipStream_t s, const void* u, const void* const* st) {
+  // the J^T part of the RK-3 adjoint step from u and its stage states st = {U2, U3}, updating
+  // the adjoint state lam in place (LAMB unless a caller buffer is given)
+  hipError_t enqueue_adjoint_jt_rk3(hipStream_t s, const void* u, const void* const* st, void* lam = nullptr) {
     hipError_t e;
     const Coef one{1, 0}, zero{0, 0};
-    Epi ep{b(T1), b(LAMB), {0, 2.0 / 3}, {0, 2.0}, b(LACC), b(LAMB), one, one};
-    if ((e = os->apply(OP_JACT, st[1], b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
-    ep = Epi{b(T2), b(LAMB), {0, 7.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one, {0, -1.0}, zero};
+    void* L = lam ? lam : b(LAMB);
+    Epi ep{b(T1), L, {0, 2.0 / 3}, {0, 2.0}, b(LACC), L, one, one};
+    if ((e = os->apply(OP_JACT, st[1], L, {0, 1.0 / 6}, ep, s))) return e;
+    ep = Epi{b(T2), L, {0, 7.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one, {0, -1.0}, zero};
     if ((e = os->apply(OP_JACT, st[0], b(T1), one, ep, s))) return e;
-    ep = Epi{b(LAMB), b(LACC), one, one, nullptr, nullptr, zero, zero};
+    ep = Epi{L, b(LACC), one, one, nullptr, nullptr, zero, zero};
     return os->apply(OP_JACT, u, b(T2), one, ep, s);
   }
 
@@ -538,17 +540,19 @@ struct Integrator {
     const void* st[3] = {b(A2), b(A3), b(A4)};
     return enqueue_adjoint_jt_rk4(s, b(USTATE), st);
   }
-  // the J^T part of the RK4 adjoint step from u and its stage states st = {U2, U3, U4}
-  hipError_t enqueue_adjoint_jt_rk4(hipStream_t s, const void* u, const void* const* st) {
+  // the J^T part of the RK4 adjoint step from u and its stage states st = {U2, U3, U4}, updating
+  // the adjoint state lam in place (LAMB unless a caller buffer is given)
+  hipError_t enqueue_adjoint_jt_rk4(hipStream_t s, const void* u, const void* const* st, void* lam = nullptr) {
     hipError_t e;
     const Coef one{1, 0}, zero{0, 0};
-    Epi ep{b(T1), b(LAMB), {0, 1.0 / 3}, {0, 1.0}, b(LACC), b(LAMB), one, one};
-    if ((e = os->apply(OP_JACT, st[2], b(LAMB), {0, 1.0 / 6}, ep, s))) return e;
-    ep = Epi{b(T2), b(LAMB), {0, 1.0 / 3}, {0, 0.5}, b(LACC), b(LACC), one, one};
+    void* L = lam ? lam : b(LAMB);
+    Epi ep{b(T1), L, {0, 1.0 / 3}, {0, 1.0}, b(LACC), L, one, one};
+    if ((e = os->apply(OP_JACT, st[2], L, {0, 1.0 / 6}, ep, s))) return e;
+    ep = Epi{b(T2), L, {0, 1.0 / 3}, {0, 0.5}, b(LACC), b(LACC), one, one};
     if ((e = os->apply(OP_JACT, st[1], b(T1), one, ep, s))) return e;
-    ep = Epi{b(T1), b(LAMB), {0, 1.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one};
+    ep = Epi{b(T1), L, {0, 1.0 / 6}, {0, 0.5}, b(LACC), b(LACC), one, one};
     if ((e = os->apply(OP_JACT, st[0], b(T2), one, ep, s))) return e;
-    ep = Epi{b(LAMB), b(LACC), one, one, nullptr, nullptr, zero, zero};
+    ep = Epi{L, b(LACC), one, one, nullptr, nullptr, zero, zero};
     return os->apply(OP_JACT, u, b(T1), one, ep, s);
   }
 
@@ -703,19 +707,25 @@ struct Integrator {
     }
     return SEM_OK;
   }
+  // The adjoint state is updated in the caller's buffer (in: lam_T, out: lam_0), so no copy in
+  // or out: these launches are not captured, so they may take any buffer.  lam must therefore not
+  // overlap the stage states, which are read until the last step.
   int adjoint_stored(int scheme, const void* stages, int32_t nsteps, void* lam, hipStream_t s) {
     if (nsteps == 0) return SEM_OK;
-    const size_t bytes = (size_t)n * ts;
     const int ns = stage_states(scheme);
+    {
+      const char* s0 = static_cast<const char*>(stages);
+      const char* s1 = s0 + (size_t)nsteps * ns * n * ts;
+      const char* l0 = static_cast<const char*>(lam);
+      if (l0 < s1 && s0 < l0 + (size_t)n * ts) return fail(SEM_ERR_ARG, "lam overlaps the stage states");
+    }
     void* sb = const_cast<void*>(stages);  // read only
-    HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
     for (int k = nsteps - 1; k >= 0; --k) {
       const void* st[3] = {stage_slot(sb, scheme, k, 1), stage_slot(sb, scheme, k, 2),
                            ns > 3 ? stage_slot(sb, scheme, k, 3) : nullptr};
       const void* uk = stage_slot(sb, scheme, k, 0);
-      HIPCHK(scheme == SEM_RK3 ? enqueue_adjoint_jt_rk3(s, uk, st) : enqueue_adjoint_jt_rk4(s, uk, st));
+      HIPCHK(scheme == SEM_RK3 ? enqueue_adjoint_jt_rk3(s, uk, st, lam) : enqueue_adjoint_jt_rk4(s, uk, st, lam));
     }
-    HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
     return SEM_OK;
   }
 

@@ -463,6 +463,8 @@ def test_stored_stages_batch_and_errors(P):
         c.rk_adjoint_stored(st, 1e-3, 3, u)  # stage array of another length
     with pytest.raises(P.SemError):
         P.sem._call(P.lib().sem_rk_adjoint_stored(c._h, 0, P.sem._ptr(st), 1e-3, 2, P.sem._ptr(st)))  # aliasing
+    with pytest.raises(P.SemError):  # lam inside the stage states (updated in place, so refused)
+        P.sem._call(P.lib().sem_rk_adjoint_stored(c._h, 0, P.sem._ptr(st), 1e-3, 2, P.sem._ptr(st.view(-1)[7:])))
 
 
 @pytest.mark.parametrize("dim,N,E,batch", [(1, 8, [16], 2), (2, 7, [8, 3], 1), (2, 9, [5, 4], 2), (3, 7, [4, 2, 3], 1),
