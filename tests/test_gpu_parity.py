@@ -363,12 +363,14 @@ def test_trajectory_stored_tail(P, scheme, N):
 @pytest.mark.parametrize("dim,N,E,batch", [(2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1), (2, 7, [3, 3], 1),
                                            (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2),
                                            (2, 7, [8, 3], 2), (2, 7, [8, 1], 1), (2, 5, [8, 2], 2),
-                                           (2, 9, [32, 2], 2), (2, 9, [8, 3], 1), (3, 7, [8, 2, 3], 1)])
+                                           (2, 9, [32, 2], 2), (2, 9, [8, 3], 1), (3, 7, [8, 2, 3], 1),
+                                           (3, 7, [12, 2, 2], 2)])
 def test_rk4_forward_adjoint(P, dim, N, E, batch):
     note(f"RK4 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
     # order 9 takes a 4x smaller step (RK4 at 2e-3 is unstable there: the oracle diverges) and the
-    # 32-element rows a domain stretched along x
-    L = [E[0] / 8.0, 1.0] if N == 9 and E[0] > 16 else None
+    # 32-element rows a domain stretched along x; 3-D rows of more than 8 elements keep h_x = 1/4
+    # (on the unit cube the 12-element row's oracle trajectory grows past 400 within 20 steps)
+    L = [E[0] / 8.0, 1.0] if N == 9 and E[0] > 16 else [E[0] / 4.0, 1.0, 1.0] if dim == 3 and E[0] > 8 else None
     m, c = make(P, dim, N, E, nu=0.01, batch=batch, L=L)
     u, _, w = fields(m, 17)
     dt, n, K = (5e-4 if N == 9 else 2e-3), 20, 5
@@ -765,10 +767,11 @@ def test_batch_trajectory_gradient(P):
 # ------------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("dim,N,E,batch", [(1, 8, [16], 1), (2, 5, [4, 3], 2), (3, 4, [2, 2, 3], 1),
                                            (3, 7, [3, 2, 4], 1), (3, 7, [4, 2, 3], 1), (3, 7, [4, 1, 2], 2),
-                                           (2, 7, [8, 2], 2), (2, 3, [8, 3], 1)])
+                                           (2, 7, [8, 2], 2), (2, 3, [8, 3], 1), (3, 7, [12, 2, 2], 2)])
 def test_rk3_forward_adjoint(P, dim, N, E, batch):
     note(f"RK-3 forward/adjoint dim={dim} N={N} E={E} batch={batch}")
-    m, c = make(P, dim, N, E, nu=0.01, batch=batch)
+    L = [E[0] / 4.0, 1.0, 1.0] if dim == 3 and E[0] > 8 else None  # as in test_rk4_forward_adjoint
+    m, c = make(P, dim, N, E, nu=0.01, batch=batch, L=L)
     u, _, w = fields(m, 19)
     dt, n, K = (2e-3 if dim > 1 else 2e-4), 20, 5  # the 1-D N=8 mesh on [0, 1] needs the smaller step
     uT_ref, ck_ref = m.erk_forward("rk3", u, dt, n, K)
