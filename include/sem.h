@@ -138,8 +138,9 @@ int sem_rk4_forward_noalloc(sem_ctx ctx, void* u, double dt, int32_t nsteps, int
    step, as an adjoint with stored stages), and each adjoint step then only applies the four J^T
    products; smaller states keep one state per step and recompute the stage states in each
    adjoint step (3 F more per step, but every step is one captured graph).  Both give the same
-   values; sem_set_adjoint_stages overrides the choice.  With nsteps = 0, lam is left unchanged
-   and ckpt may be NULL (as for every adjoint entry point below). */
+   values; sem_set_adjoint_stages overrides the choice.  With stored stages lam is updated in place
+   through the sweep, so lam overlapping ckpt or work is SEM_ERR_ARG.  With nsteps = 0, lam is
+   left unchanged and ckpt may be NULL (as for every adjoint entry point below). */
 int sem_rk4_adjoint(sem_ctx ctx, const void* ckpt, double dt, int32_t nsteps, int32_t ckpt_every,
                     void* lam, void* work);
 /* The same two calls for any sem_scheme: the stage updates of every scheme are fused into the

@@ -651,27 +651,36 @@ struct Integrator {
   int adjoint(int scheme, const void* ckpt, int32_t nsteps, int32_t K, void* lam, void* work, hipStream_t s) {
     const size_t bytes = n * ts;
     char* wk = static_cast<char*>(work);
-    HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
     if (stores_stages()) {
-      // work: [K][stage_states][n]; slot (k, 0) holds u_k, slots (k, 1..) its stage states
+      // work: [K][stage_states][n]; slot (k, 0) holds u_k (k >= 1; u_0 is read from its
+      // checkpoint), slots (k, 1..) its stage states.  These launches are not captured, so the
+      // adjoint state is updated in the caller's buffer (no copy in or out); it must not overlap
+      // the checkpoints or the work slots, which are read until the last step.
       const int ns = stage_states(scheme);
+      {
+        const char* l0 = static_cast<const char*>(lam);
+        const char* c0 = static_cast<const char*>(ckpt);
+        const size_t cb = (size_t)(nsteps / K) * bytes, wb = (size_t)K * ns * bytes;
+        if ((nsteps > 0 && l0 < c0 + cb && c0 < l0 + bytes) || (l0 < wk + wb && wk < l0 + bytes))
+          return fail(SEM_ERR_ARG, "lam overlaps the checkpoints or the work buffer");
+      }
       auto slot = [&](int k, int j) -> void* { return wk + ((size_t)k * ns + j) * bytes; };
       for (int sg = nsteps / K - 1; sg >= 0; --sg) {
-        HIPCHK(hipMemcpyAsync(slot(0, 0), static_cast<const char*>(ckpt) + (size_t)sg * bytes, bytes,
-                              hipMemcpyDeviceToDevice, s));
+        const void* u0 = static_cast<const char*>(ckpt) + (size_t)sg * bytes;
+        auto state = [&](int k) -> const void* { return k == 0 ? u0 : slot(k, 0); };
         for (int k = 0; k < K; ++k) {
           void* st[3] = {slot(k, 1), slot(k, 2), ns > 3 ? slot(k, 3) : nullptr};
-          HIPCHK(enqueue_step_stages(s, scheme, slot(k, 0), st, k + 1 < K ? slot(k + 1, 0) : nullptr));
+          HIPCHK(enqueue_step_stages(s, scheme, state(k), st, k + 1 < K ? slot(k + 1, 0) : nullptr));
         }
         for (int k = K - 1; k >= 0; --k) {
           const void* st[3] = {slot(k, 1), slot(k, 2), ns > 3 ? slot(k, 3) : nullptr};
-          HIPCHK(scheme == SEM_RK3 ? enqueue_adjoint_jt_rk3(s, slot(k, 0), st)
-                                   : enqueue_adjoint_jt_rk4(s, slot(k, 0), st));
+          HIPCHK(scheme == SEM_RK3 ? enqueue_adjoint_jt_rk3(s, state(k), st, lam)
+                                   : enqueue_adjoint_jt_rk4(s, state(k), st, lam));
         }
       }
-      HIPCHK(hipMemcpyAsync(lam, b(LAMB), bytes, hipMemcpyDeviceToDevice, s));
       return SEM_OK;
     }
+    HIPCHK(hipMemcpyAsync(b(LAMB), lam, bytes, hipMemcpyDeviceToDevice, s));
     for (int sg = nsteps / K - 1; sg >= 0; --sg) {
       HIPCHK(hipMemcpyAsync(b(STATE), static_cast<const char*>(ckpt) + (size_t)sg * bytes, bytes,
                             hipMemcpyDeviceToDevice, s));

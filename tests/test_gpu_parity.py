@@ -467,6 +467,17 @@ def test_stored_stages_batch_and_errors(P):
         P.sem._call(P.lib().sem_rk_adjoint_stored(c._h, 0, P.sem._ptr(st), 1e-3, 2, P.sem._ptr(st)))  # aliasing
     with pytest.raises(P.SemError):  # lam inside the stage states (updated in place, so refused)
         P.sem._call(P.lib().sem_rk_adjoint_stored(c._h, 0, P.sem._ptr(st), 1e-3, 2, P.sem._ptr(st.view(-1)[7:])))
+    # the checkpointed adjoint that stores stage states also updates lam in place
+    c.set_adjoint_stages("store")
+    _, ck = c.rk_forward(u, 1e-3, 2, 1)
+    wk = torch.empty(c.workspace_bytes(1) // 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(P.SemError):  # lam inside the work buffer
+        P.sem._call(P.lib().sem_rk_adjoint(c._h, 0, P.sem._ptr(ck), 1e-3, 2, 1, P.sem._ptr(wk.view(-1)[3:]),
+                                           P.sem._ptr(wk)))
+    with pytest.raises(P.SemError):  # lam inside the checkpoints
+        P.sem._call(P.lib().sem_rk_adjoint(c._h, 0, P.sem._ptr(ck), 1e-3, 2, 1, P.sem._ptr(ck.view(-1)[3:]),
+                                           P.sem._ptr(wk)))
+    c.set_adjoint_stages("auto")
 
 
 @pytest.mark.parametrize("dim,N,E,batch", [(1, 8, [16], 2), (2, 7, [8, 3], 1), (2, 9, [5, 4], 2), (3, 7, [4, 2, 3], 1),
