@@ -71,6 +71,8 @@ CASES = [
     # order 7 with an x element count that is a multiple of 4 runs the tuned 3-D kernel
     (3, 7, [4, 1, 1]), (3, 7, [4, 2, 3]), (3, 7, [8, 3, 2]), (3, 7, [4, 5, 1]), (3, 7, [12, 1, 2]),
     (3, 7, [8, 2, 5]), (3, 7, [4, 4, 4]),
+    # 8 workgroups per field and z-segment: the XCD-banded workgroup order is active
+    (3, 7, [16, 2, 2]), (3, 7, [8, 4, 3]),
     # orders 3, 5, 7 with an x element count that is a multiple of 8 (at most 64) run the tuned
     # 2-D kernel: one or several wavefronts per workgroup, one element row, ragged row segments
     (2, 7, [8, 1]), (2, 7, [8, 2]), (2, 7, [8, 3]), (2, 7, [16, 5]), (2, 7, [24, 2]),
