@@ -37,7 +37,7 @@
 //      the corner line both rules apply (the diagonal element's terms are the doubled y-term of
 //      the lower and x-term of the left element).  The upper and right faces are left to the
 //      workgroups that own them.
-//   workgroup faces of the plain J v and J^T and of the segmented FP32 J^T (face_buffer_variant):
+//   workgroup faces of the segmented FP32 J^T (face_buffer_variant):
 //      the workgroup writes its finished nodes to the output and, to a face buffer, its partial sums of the lower y-row (y = 7ey), its contributions to the upper
 //      y-row and upper x-column (owned by the neighbours), and the first 32-byte sector of each
 //      interior row (x in [28X, 28X + 4): the x = 28X node still lacks the left neighbour's
@@ -80,17 +80,15 @@ struct FastArgs {
 // 32-bit accesses with all 64 lanes at once).
 __device__ __forceinline__ int tix(int a, int b, int c) { return (c << 6) + ((b ^ c) << 3) + (a ^ b); }
 
-// The variants that leave their workgroup faces to the face buffer and fast3d_fixup:
-//   the plain J v and J^T (no epilogue): completing the faces in the kernel takes them exactly as
-//     long (the neighbour lines, loaded where they are used, expose their latency) and re-reads
-//     the neighbour rows from beyond the L2, 1.44 GB per J^T apply against 1.14 GB with the face
-//     buffer;
-//   the segmented J^T (FP32): its register budget (two wavefronts per SIMD) leaves no room for the
-//     neighbours' lines.
-// With a stage epilogue J v and J^T complete their faces: the fixup would read the epilogue
-// operands of its nodes as scattered sectors, and there the in-kernel completion is faster.
+// The variant that leaves its workgroup faces to the face buffer and fast3d_fixup: the segmented
+// J^T (FP32), whose register budget (two wavefronts per SIMD) leaves no room for the neighbours'
+// lines.  Every other variant completes its faces in the kernel.  With a stage epilogue the fixup
+// would read the epilogue operands of its nodes as scattered sectors; the plain J v and J^T
+// complete theirs too since their lower state lines are loaded a step ahead (J^T 402 -> 393 us,
+// J v 407 -> 379 us per apply on the 32^3 field, against main kernel + fixup).
 constexpr bool face_buffer_variant(int op, int ep, bool seg) {
-  return (op != OP_RHS && ep == 0) || (seg && op == OP_JACT);
+  (void)ep;
+  return seg && op == OP_JACT;
 }
 
 // EP: epilogue variant known at compile time: 0 = o1 = b1 s; 1 = o1 = a1 x1 + b1 s;
@@ -704,6 +702,11 @@ bool fast3d_supported(const ProbDev& hp) {
          (int64_t)3 * hp.nodes * 8 < ((int64_t)1 << 31);
 }
 
+
+bool fast3d_needs_face(const ProbDev& hp, bool f32) {
+  return fast3d_face_buffer(hp, OP_JACT, 0, f32) || fast3d_face_buffer(hp, OP_JAC, 0, f32) ||
+         fast3d_face_buffer(hp, OP_RHS, 0, f32);
+}
 
 int64_t fast3d_face_values(const ProbDev& hp) {
   return (int64_t)hp.batch * (hp.E[0] / WX) * hp.E[1] * 3 * hp.n[2] * FROWS;

@@ -401,7 +401,9 @@ int build_opset(OpSet& os, const sem_desc* descs, int count, bool allow_fast) {
     fast_fill_tables(descs[0].order, host.data());
     if ((rc = os.fast_tab.alloc(host.size()))) return rc;
     HIPCHK(hipMemcpy(os.fast_tab.p, host.data(), host.size(), hipMemcpyHostToDevice));
-    if (os.fast == 3 && (rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts))) return rc;
+    if (os.fast == 3 && fast3d_needs_face(os.hp[0], os.dtype == SEM_F32) &&
+        (rc = os.face.alloc(fast3d_face_values(os.hp[0]) * os.ts)))
+      return rc;
     if (os.fast == 2) HIPCHK(fast2d_prepare(descs[0].order, os.dtype));
   }
   return os.finalize();

@@ -97,12 +97,13 @@ int persist2d_elems_per_item(int P);  // elements per work item for order P
 // Host GLL tables in long double (gll.cpp)
 void gll_tables(int N, double* xi, double* w, double* D);
 
-// Tuned paths (kern_fast3d.hip: 3-D order 7; kern_fast2d.hip: 2-D orders 3, 5, 7) for one
+// Tuned paths (kern_fast3d.hip: 3-D order 7; kern_fast2d.hip: 2-D orders 3, 5, 7, 9) for one
 // problem (any batch).  The epilogue output o1 must alias neither operator input: other
 // workgroups still read the input nodes that a workgroup has finished.  Both take the device
 // table of their order (fast_fill_tables).
 bool fast3d_supported(const ProbDev& hp);
 int64_t fast3d_face_values(const ProbDev& hp);
+bool fast3d_needs_face(const ProbDev& hp, bool f32);  // whether any 3-D launch uses the face buffer
 
 // FP64 rate diagnostic (kern_probe.hip): mode 0 matrix cores, 1 vector FMAs, 2 both interleaved;
 // `out` holds fp64_probe_values() doubles.
