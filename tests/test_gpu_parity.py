@@ -266,7 +266,7 @@ def test_full_size_3d(P, dtype):
 
 def test_full_size_3d_trajectory(P):
     # the 32^3 N=7 field through the fused RK4 stage kernels (every epilogue variant of the tuned
-    # 3-D kernel and its fixup) and the discrete adjoint, at the benchmark's step size
+    # 3-D kernel) and the discrete adjoint, at the benchmark's step size
     cfg = wl.C3
     note("full-size 3-D 32^3 N=7 FP64: 3 RK4 steps + adjoint (checkpointed and stored stages)")
     m = oracle.Mesh(3, cfg.N, list(cfg.E), list(cfg.L), cfg.nu)
